@@ -1,0 +1,209 @@
+/*
+ * relapack.h -- C ABI of librelapack_mi355x.so, recursive dense factorizations
+ * for AMD MI355X (gfx950).
+ *
+ * The operations are those of the ReLAPACK collection (Peise & Bientinesi,
+ * "Recursive Algorithms for Dense Linear Algebra: The ReLAPACK Collection"):
+ * recursive Cholesky (xpotrf, Sec. 5) and recursive LU with partial pivoting
+ * (xgetrf, Sec. 5), built as the paper prescribes (Sec. 3): the blocked
+ * algorithm with block size n/2 and the unblocked kernel replaced by a
+ * recursive call, halves aligned to a fixed quantum where possible, an
+ * unblocked kernel below a fixed crossover size, no block-size tuning. Almost
+ * every flop lands in the BLAS-3 updates of the top recursion levels (Sec. 3,
+ * flop-share analysis next to Fig. recursive_breakdown), which here run on the
+ * FP64 matrix cores. The argument conventions are LAPACK's, whose interface
+ * the paper keeps (Sec. 5, first paragraph).
+ *
+ * Conventions common to every entry point
+ *   - Matrices and pivot vectors (A, B, X, C, ipiv, d, r, c, S) are DEVICE
+ *     pointers (hipMalloc or a torch CUDA tensor's data_ptr()), column-major
+ *     with the given leading dimension. The caller owns them.
+ *   - Scalar outputs (info, iter, berr) are HOST pointers. A NULL info makes
+ *     the call a no-op.
+ *   - Every call is stream-ordered on the calling thread's library stream
+ *     (relapack_set_stream) and returns after the work has completed, so info
+ *     is valid on return.
+ *   - info = 0: success. info = -k: argument k (counted in the C signature
+ *     order below) is illegal; nothing was launched. info in (-2000, -1000]:
+ *     a HIP runtime error e was reported (info = -1000 - e). info <= -2000:
+ *     an internal wait of the LU panel timed out (the result is unusable).
+ *   - The library keeps a grow-only device workspace per device (status
+ *     block, pivot bookkeeping, low-precision copies); relapack_finalize()
+ *     releases it.
+ *   - Integer arguments are 32-bit as in LAPACK; index arithmetic inside is
+ *     64-bit.
+ */
+#ifndef RELAPACK_MI355X_H
+#define RELAPACK_MI355X_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Library version (1). */
+int relapack_version(void);
+
+/* Set the calling thread's stream (a hipStream_t; NULL = the null stream).
+ * Returns 0. */
+int relapack_set_stream(void *hip_stream);
+
+/* The calling thread's stream. */
+void *relapack_get_stream(void);
+
+/* Free the per-device workspace of every device the library has touched. */
+void relapack_finalize(void);
+
+/*
+ * Cholesky factorization (xpotrf; Sec. 5 and Fig. bvsr_others):
+ *   uplo = 'L': A = L·Lᵀ, L overwrites the lower triangle;
+ *   uplo = 'U': A = Uᵀ·U, U overwrites the upper triangle.
+ * The strict other triangle is neither read nor written.
+ * A: n×n, lda >= max(1, n).
+ * info = k > 0: the leading minor of order k is not positive definite (its
+ * pivot is <= 0 or NaN); every kernel after the failing leaf returns at once,
+ * so columns before k hold the factor and column k holds its updated pivot.
+ * Errors: uplo -1, n -2, lda -4.
+ */
+void relapack_dpotrf(char uplo, int n, double *A, int lda, int *info);
+
+/*
+ * LU factorization with partial (row) pivoting (xgetrf; Sec. 5): A = P·L·U,
+ * L unit lower trapezoidal (m×min(m,n)), U upper trapezoidal; both overwrite
+ * A. ipiv (device, min(m,n) ints, 1-based): row i was interchanged with row
+ * ipiv[i], in order. The pivot is the first row holding the largest |a_ik|
+ * (a NaN never wins).
+ * info = k > 0: U(k,k) is exactly zero (the first such k); the factorization
+ * is completed.
+ * Errors: m -1, n -2, lda -4.
+ */
+void relapack_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info);
+
+/*
+ * Solve A·X = B with the factor from relapack_dpotrf (xpotrs). A: the n×n
+ * factor; B: n×nrhs, overwritten by X.
+ * Errors: uplo -1, n -2, nrhs -3, lda -5, ldb -7.
+ */
+void relapack_dpotrs(char uplo, int n, int nrhs, const double *A, int lda, double *B, int ldb,
+                     int *info);
+
+/*
+ * Solve A·X = B (trans 'N') or Aᵀ·X = B (trans 'T'/'C') with the factors and
+ * pivots from relapack_dgetrf of a square A (xgetrs). B: n×nrhs, overwritten.
+ * Errors: trans -1, n -2, nrhs -3, lda -5, ldb -8.
+ */
+void relapack_dgetrs(char trans, int n, int nrhs, const double *A, int lda, const int *ipiv,
+                     double *B, int ldb, int *info);
+
+/*
+ * Mixed-precision solve of an SPD system with FP64 iterative refinement.
+ * A (n×n, only the uplo triangle is read, never modified), B (n×nrhs, read),
+ * X (n×nrhs, written). The factorization runs on a power-of-two scaled copy
+ * D·A·D held in FP32 with its matrix-core updates in the arithmetic prec:
+ * 32 (FP32), 16 (FP16 operands, FP32 accumulation) or 'b' (BF16 operands,
+ * FP32 accumulation). FP64 is used for the residual r = b - A·x, the update
+ * and the correction solve. Stops when every column's normwise backward error
+ * eta = ||r||inf / (||A||inf·||x||inf + ||b||inf) <= 1e-14.
+ * iter (host): > 0 refinement sweeps used; < 0 the FP64 path was used
+ * instead: -3 the low-precision factorization failed, -31 no convergence.
+ * berr (host): the final max_j eta_j, computed in FP64.
+ * Errors: uplo -1, n -2, nrhs -3, lda -5, ldb -7, ldx -9, prec -10.
+ */
+void relapack_dposv_mixed(char uplo, int n, int nrhs, const double *A, int lda, const double *B,
+                          int ldb, double *X, int ldx, int prec, int *iter, double *berr,
+                          int *info);
+
+/*
+ * Mixed-precision solve of a general system with FP64 iterative refinement;
+ * as relapack_dposv_mixed with a partial-pivoting LU of the two-sided
+ * power-of-two scaled copy R·A·C in FP32. ipiv (device, n ints) receives the
+ * low-precision factorization's pivots (or the FP64 ones after a fallback).
+ * Errors: n -1, nrhs -2, lda -4, ldb -7, ldx -9, prec -10.
+ */
+void relapack_dgesv_mixed(int n, int nrhs, const double *A, int lda, int *ipiv, const double *B,
+                          int ldb, double *X, int ldx, int prec, int *iter, double *berr,
+                          int *info);
+
+/* ---- building blocks on the recursion's path (FP64 matrix cores) -------- */
+
+/*
+ * C := beta·C + alpha·op(A)·op(B), op = 'N' or 'T' (xgemm; the Schur-complement
+ * updates of the recursion, Sec. 3). C: m×n.
+ * Errors: transa -1, transb -2, m -3, n -4, k -5, lda -8, ldb -10, ldc -13.
+ */
+void relapack_dgemm(char transa, char transb, int m, int n, int k, double alpha, const double *A,
+                    int lda, const double *B, int ldb, double beta, double *C, int ldc, int *info);
+
+/*
+ * C := beta·C + alpha·op(A)·op(A)ᵀ on the uplo triangle of C only (xsyrk;
+ * Cholesky's trailing update). trans 'N': op(A) = A (n×k); 'T': op(A) = Aᵀ.
+ * Errors: uplo -1, trans -2, n -3, k -4, lda -7, ldc -10.
+ */
+void relapack_dsyrk(char uplo, char trans, int n, int k, double alpha, const double *A, int lda,
+                    double beta, double *C, int ldc, int *info);
+
+/*
+ * Triangular solve with many right-hand sides, B := op(A)⁻¹·B (side 'L') or
+ * B := B·op(A)⁻¹ (side 'R') (xtrsm with alpha = 1), recursive down to a
+ * substitution leaf. A: triangular (uplo), unit diagonal if diag = 'U'.
+ * Errors: side -1, uplo -2, transa -3, diag -4, m -5, n -6, lda -8, ldb -10.
+ */
+void relapack_dtrsm(char side, char uplo, char transa, char diag, int m, int n, const double *A,
+                    int lda, double *B, int ldb, int *info);
+
+/* ---- pieces of the mixed-precision path -------------------------------- */
+
+/*
+ * Power-of-two symmetric scaling and conversion: d_i = 2^-t_i with
+ * 4^t_i <= a_ii < 4^(t_i+1) (d_i = 1 if a_ii is not positive and finite);
+ * S = D·A·D rounded to FP32 (round to nearest even) in the uplo triangle.
+ * d: n doubles; S: n×n floats, lds >= max(1, n). Errors: uplo -1, n -2, lda -4, lds -7.
+ */
+void relapack_scale_spd_f32(char uplo, int n, const double *A, int lda, double *d, float *S, int lds,
+                            int *info);
+
+/*
+ * Two-sided power-of-two scaling and conversion: r_i = 2^-t with
+ * 2^t <= max_j |a_ij| < 2^(t+1), then c_j the same for the columns of R·A
+ * (1 for an all-zero row or column); S = R·A·C rounded to FP32.
+ * Errors: n -1, lda -3, lds -7.
+ */
+void relapack_scale_ge_f32(int n, const double *A, int lda, double *r, double *c, float *S, int lds,
+                           int *info);
+
+/*
+ * Recursive Cholesky / partial-pivoting LU of an FP32 matrix whose
+ * matrix-core updates use the arithmetic prec (32, 16 or 'b'; FP32
+ * accumulation). Same argument and info conventions as the FP64 routines;
+ * prec is argument -5 (potrf) / -6 (getrf).
+ */
+void relapack_spotrf_lp(char uplo, int n, float *A, int lda, int prec, int *info);
+void relapack_sgetrf_lp(int m, int n, float *A, int lda, int *ipiv, int prec, int *info);
+
+/* ---- measurement and inspection ------------------------------------------ */
+
+/* Bracket every kernel launch of this thread with HIP events (on = 1) and
+ * clear the collected records. */
+void relapack_trace_enable(int on);
+
+/* Per kernel family k in [0, cap): out[4k .. 4k+3] = {launches, total ms,
+ * algorithmic flops, algorithmic bytes}; families: 1 potf2, 2 trsm leaf,
+ * 3 gemm, 4 syrk (FP64 matrix cores), 5 getf2 panel, 6 laswp, 7 convert,
+ * 8 residual, 10 gemm and 11 syrk with FP32/FP16/BF16 operands. Synchronizes
+ * the stream and clears the records. Returns cap, or -1 on a HIP error. */
+int relapack_trace_collect(double *out, int cap);
+
+/* The kernel-call sequence of one factorization without launching anything
+ * (no GPU needed): routine "potrf_L", "potrf_U" or "getrf"; leaf > 0
+ * overrides every crossover size. Writes up to cap records of 5 int64
+ * {kind, depth, m, n, k} to rec; returns the total number of calls. */
+long long relapack_plan(const char *routine, long long m, long long n, int leaf, long long *rec,
+                        long long cap);
+
+/* Size of the first half when the recursion splits n (host rule, no GPU). */
+long long relapack_split(long long n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RELAPACK_MI355X_H */

@@ -1,0 +1,260 @@
+"""Python binding of librelapack_mi355x.so (argument marshalling only).
+
+Every function here forwards to the C ABI declared in ``include/relapack.h``
+with the same name minus the ``relapack_`` prefix. Matrices are passed as
+device pointers: either raw integers or torch CUDA tensors (their
+``data_ptr()``), column-major, i.e. a tensor ``t`` whose ``t.T`` is
+contiguous (``t.stride() == (1, ld)``). Nothing here computes: there is no
+CPU fallback, and loading fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librelapack_mi355x.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "relapack.h")
+
+_lib = None
+
+_c_int, _c_char, _c_double, _c_ll = ctypes.c_int, ctypes.c_char, ctypes.c_double, ctypes.c_longlong
+_vp = ctypes.c_void_p
+_ip = ctypes.POINTER(ctypes.c_int)
+_dp = ctypes.POINTER(ctypes.c_double)
+_llp = ctypes.POINTER(ctypes.c_longlong)
+
+_SIGS = {
+    "relapack_version": ([], _c_int),
+    "relapack_set_stream": ([_vp], _c_int),
+    "relapack_get_stream": ([], _vp),
+    "relapack_finalize": ([], None),
+    "relapack_dpotrf": ([_c_char, _c_int, _vp, _c_int, _ip], None),
+    "relapack_dgetrf": ([_c_int, _c_int, _vp, _c_int, _vp, _ip], None),
+    "relapack_dpotrs": ([_c_char, _c_int, _c_int, _vp, _c_int, _vp, _c_int, _ip], None),
+    "relapack_dgetrs": ([_c_char, _c_int, _c_int, _vp, _c_int, _vp, _vp, _c_int, _ip], None),
+    "relapack_dposv_mixed": ([_c_char, _c_int, _c_int, _vp, _c_int, _vp, _c_int, _vp, _c_int, _c_int,
+                              _ip, _dp, _ip], None),
+    "relapack_dgesv_mixed": ([_c_int, _c_int, _vp, _c_int, _vp, _vp, _c_int, _vp, _c_int, _c_int, _ip,
+                              _dp, _ip], None),
+    "relapack_dgemm": ([_c_char, _c_char, _c_int, _c_int, _c_int, _c_double, _vp, _c_int, _vp, _c_int,
+                        _c_double, _vp, _c_int, _ip], None),
+    "relapack_dsyrk": ([_c_char, _c_char, _c_int, _c_int, _c_double, _vp, _c_int, _c_double, _vp, _c_int,
+                        _ip], None),
+    "relapack_dtrsm": ([_c_char, _c_char, _c_char, _c_char, _c_int, _c_int, _vp, _c_int, _vp, _c_int, _ip],
+                       None),
+    "relapack_scale_spd_f32": ([_c_char, _c_int, _vp, _c_int, _vp, _vp, _c_int, _ip], None),
+    "relapack_scale_ge_f32": ([_c_int, _vp, _c_int, _vp, _vp, _vp, _c_int, _ip], None),
+    "relapack_spotrf_lp": ([_c_char, _c_int, _vp, _c_int, _c_int, _ip], None),
+    "relapack_sgetrf_lp": ([_c_int, _c_int, _vp, _c_int, _vp, _c_int, _ip], None),
+    "relapack_trace_enable": ([_c_int], None),
+    "relapack_trace_collect": ([_dp, _c_int], _c_int),
+    "relapack_plan": ([ctypes.c_char_p, _c_ll, _c_ll, _c_int, _llp, _c_ll], _c_ll),
+    "relapack_split": ([_c_ll], _c_ll),
+}
+
+TRACE_FAMILIES = {1: "potf2", 2: "trsm_leaf", 3: "gemm", 4: "syrk", 5: "getf2_panel", 6: "laswp",
+                  7: "convert", 8: "residual", 10: "gemm_lowprec", 11: "syrk_lowprec"}
+
+PREC = {"fp32": 32, "32": 32, 32: 32, "fp16": 16, "16": 16, 16: 16, "bf16": ord("b"), "b": ord("b")}
+
+
+class LibraryNotBuilt(RuntimeError):
+    pass
+
+
+def lib() -> ctypes.CDLL:
+    """Load the built library (never builds, never falls back)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryNotBuilt(
+                f"{LIB_PATH} is missing: run `python -c 'import __graft_entry__ as g; g.build()'` first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _ld(t, rows):
+    """Leading dimension of a column-major tensor (stride(0) == 1)."""
+    if isinstance(t, int):
+        return rows
+    if t.dim() == 1:
+        return max(rows, 1)
+    if t.stride(0) != 1 and t.shape[0] > 1:
+        raise ValueError("matrix must be column-major: use t.T.contiguous().T")
+    return max(int(t.stride(1)), 1) if t.shape[1] > 1 else max(rows, 1)
+
+
+def _b(ch: str) -> bytes:
+    return ch.encode() if isinstance(ch, str) else bytes([ch])
+
+
+def _cur_stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def set_stream(stream=None) -> int:
+    """Set the library stream; default: torch's current stream."""
+    if stream is None:
+        s = _cur_stream()
+    elif isinstance(stream, int):
+        s = ctypes.c_void_p(stream)
+    else:
+        s = ctypes.c_void_p(stream.cuda_stream)
+    return lib().relapack_set_stream(s)
+
+
+def version() -> int:
+    return lib().relapack_version()
+
+
+def finalize() -> None:
+    lib().relapack_finalize()
+
+
+def potrf(A, uplo: str = "L", n: int | None = None, lda: int | None = None) -> int:
+    n = A.shape[0] if n is None else n
+    lda = _ld(A, n) if lda is None else lda
+    info = ctypes.c_int(0)
+    lib().relapack_dpotrf(_b(uplo), n, _ptr(A), lda, ctypes.byref(info))
+    return info.value
+
+
+def getrf(A, ipiv, m: int | None = None, n: int | None = None, lda: int | None = None) -> int:
+    m = A.shape[0] if m is None else m
+    n = A.shape[1] if n is None else n
+    lda = _ld(A, m) if lda is None else lda
+    info = ctypes.c_int(0)
+    lib().relapack_dgetrf(m, n, _ptr(A), lda, _ptr(ipiv), ctypes.byref(info))
+    return info.value
+
+
+def potrs(A, B, uplo: str = "L") -> int:
+    n, nrhs = B.shape[0], (B.shape[1] if B.dim() > 1 else 1)
+    info = ctypes.c_int(0)
+    lib().relapack_dpotrs(_b(uplo), n, nrhs, _ptr(A), _ld(A, n), _ptr(B), _ld(B, n), ctypes.byref(info))
+    return info.value
+
+
+def getrs(A, ipiv, B, trans: str = "N") -> int:
+    n, nrhs = B.shape[0], (B.shape[1] if B.dim() > 1 else 1)
+    info = ctypes.c_int(0)
+    lib().relapack_dgetrs(_b(trans), n, nrhs, _ptr(A), _ld(A, n), _ptr(ipiv), _ptr(B), _ld(B, n),
+                          ctypes.byref(info))
+    return info.value
+
+
+def posv_mixed(A, B, X, uplo: str = "L", prec=16):
+    n, nrhs = B.shape[0], (B.shape[1] if B.dim() > 1 else 1)
+    it, berr, info = ctypes.c_int(0), ctypes.c_double(0.0), ctypes.c_int(0)
+    lib().relapack_dposv_mixed(_b(uplo), n, nrhs, _ptr(A), _ld(A, n), _ptr(B), _ld(B, n), _ptr(X),
+                               _ld(X, n), PREC.get(prec, prec), ctypes.byref(it), ctypes.byref(berr),
+                               ctypes.byref(info))
+    return info.value, it.value, berr.value
+
+
+def gesv_mixed(A, ipiv, B, X, prec=16):
+    n, nrhs = B.shape[0], (B.shape[1] if B.dim() > 1 else 1)
+    it, berr, info = ctypes.c_int(0), ctypes.c_double(0.0), ctypes.c_int(0)
+    lib().relapack_dgesv_mixed(n, nrhs, _ptr(A), _ld(A, n), _ptr(ipiv), _ptr(B), _ld(B, n), _ptr(X),
+                               _ld(X, n), PREC.get(prec, prec), ctypes.byref(it), ctypes.byref(berr),
+                               ctypes.byref(info))
+    return info.value, it.value, berr.value
+
+
+def gemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc) -> int:
+    info = ctypes.c_int(0)
+    lib().relapack_dgemm(_b(transa), _b(transb), m, n, k, alpha, _ptr(A), lda, _ptr(B), ldb, beta,
+                         _ptr(C), ldc, ctypes.byref(info))
+    return info.value
+
+
+def syrk(uplo, trans, n, k, alpha, A, lda, beta, C, ldc) -> int:
+    info = ctypes.c_int(0)
+    lib().relapack_dsyrk(_b(uplo), _b(trans), n, k, alpha, _ptr(A), lda, beta, _ptr(C), ldc,
+                         ctypes.byref(info))
+    return info.value
+
+
+def trsm(side, uplo, transa, diag, m, n, A, lda, B, ldb) -> int:
+    info = ctypes.c_int(0)
+    lib().relapack_dtrsm(_b(side), _b(uplo), _b(transa), _b(diag), m, n, _ptr(A), lda, _ptr(B), ldb,
+                         ctypes.byref(info))
+    return info.value
+
+
+def scale_spd_f32(A, d, S, uplo: str = "L") -> int:
+    n = A.shape[0]
+    info = ctypes.c_int(0)
+    lib().relapack_scale_spd_f32(_b(uplo), n, _ptr(A), _ld(A, n), _ptr(d), _ptr(S), _ld(S, n),
+                                 ctypes.byref(info))
+    return info.value
+
+
+def scale_ge_f32(A, r, c, S) -> int:
+    n = A.shape[0]
+    info = ctypes.c_int(0)
+    lib().relapack_scale_ge_f32(n, _ptr(A), _ld(A, n), _ptr(r), _ptr(c), _ptr(S), _ld(S, n),
+                                ctypes.byref(info))
+    return info.value
+
+
+def spotrf_lp(A, uplo: str = "L", prec=32) -> int:
+    n = A.shape[0]
+    info = ctypes.c_int(0)
+    lib().relapack_spotrf_lp(_b(uplo), n, _ptr(A), _ld(A, n), PREC.get(prec, prec), ctypes.byref(info))
+    return info.value
+
+
+def sgetrf_lp(A, ipiv, prec=32) -> int:
+    m, n = A.shape
+    info = ctypes.c_int(0)
+    lib().relapack_sgetrf_lp(m, n, _ptr(A), _ld(A, m), _ptr(ipiv), PREC.get(prec, prec),
+                             ctypes.byref(info))
+    return info.value
+
+
+def trace_enable(on: bool = True) -> None:
+    lib().relapack_trace_enable(1 if on else 0)
+
+
+def trace_collect() -> dict:
+    cap = 16
+    out = (ctypes.c_double * (4 * cap))()
+    if lib().relapack_trace_collect(out, cap) < 0:
+        raise RuntimeError("relapack_trace_collect failed")
+    res = {}
+    for k, name in TRACE_FAMILIES.items():
+        cnt, ms, fl, by = out[4 * k: 4 * k + 4]
+        if cnt:
+            res[name] = {"launches": int(cnt), "ms": ms, "flops": fl, "bytes": by}
+    return res
+
+
+def plan(routine: str, m: int, n: int, leaf: int = 0):
+    """Kernel-call sequence of one factorization as a list of (kind, depth, m, n, k)."""
+    cnt = lib().relapack_plan(routine.encode(), m, n, leaf, None, 0)
+    if cnt < 0:
+        raise ValueError(routine)
+    buf = (ctypes.c_longlong * (5 * max(cnt, 1)))()
+    lib().relapack_plan(routine.encode(), m, n, leaf, buf, cnt)
+    return [tuple(buf[5 * i: 5 * i + 5]) for i in range(cnt)]
+
+
+def split(n: int) -> int:
+    return int(lib().relapack_split(n))

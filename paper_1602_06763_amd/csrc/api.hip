@@ -1,0 +1,578 @@
+// C ABI of the library (declared in include/relapack.h) and the per-thread /
+// per-device state behind it: stream, status block, workspace, plan
+// recording and the per-kernel-family timers.
+#include "common.hpp"
+
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+namespace rl {
+
+namespace {
+
+constexpr int kMaxDev = 16;
+constexpr int kScratchSlots = 8;
+
+struct DevState {
+    bool init = false;
+    DevStatus *dstat = nullptr;
+    DevStatus *hstat = nullptr;
+    double *panel_rec = nullptr;
+    size_t panel_rec_elems = 0;
+    int *rowsrc = nullptr;
+    size_t rowsrc_elems = 0;
+    void *slot[kScratchSlots] = {};
+    size_t slot_bytes[kScratchSlots] = {};
+    int num_cu = 256;
+    // single-launch triangular solve
+    double *trsv_x = nullptr;
+    size_t trsv_x_rows = 0;
+    int *trsv_ready = nullptr;
+    int trsv_ready_n = 0;
+    unsigned long long *trsv_ticket = nullptr;
+    unsigned long long trsv_tickets = 0;
+    int trsv_epoch = 0;
+};
+
+DevState g_dev[kMaxDev];
+std::mutex g_mu;
+
+struct TraceRec {
+    int kind;
+    double flops, bytes;
+    hipEvent_t e0, e1;
+};
+
+thread_local Ctx t_ctx;
+thread_local int t_err = 0;
+thread_local std::vector<TraceRec> t_trace;
+thread_local std::vector<hipEvent_t> t_evpool;
+thread_local size_t t_evused = 0;
+
+__global__ void fill_int_k(int *p, long long n, int v) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void zero_u64_one_k(unsigned long long *p) {
+    if (threadIdx.x == 0) *p = 0ull;
+}
+
+__global__ void reset_status_k(DevStatus *s) {
+    if (threadIdx.x == 0) { s->info = 0; s->error = 0; s->barrier = 0u; s->pad = 0; }
+}
+
+}  // namespace
+
+Ctx &ctx() { return t_ctx; }
+
+int launch_error(hipError_t e) {
+    if (!t_err) t_err = (int)e;
+    return (int)e;
+}
+
+void ensure_device(Ctx &c) {
+    int dev = 0;
+    RL_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) { launch_error(hipErrorInvalidDevice); return; }
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState &d = g_dev[dev];
+    if (!d.init) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) d.num_cu = p.multiProcessorCount;
+        RL_CHECK(hipMalloc(&d.dstat, sizeof(DevStatus)));
+        RL_CHECK(hipHostMalloc(&d.hstat, sizeof(DevStatus), hipHostMallocDefault));
+        d.panel_rec_elems = (size_t)2 * (kPanelMaxWG + 1) * (kLuLeaf + 4);
+        RL_CHECK(hipMalloc(&d.panel_rec, d.panel_rec_elems * sizeof(double)));
+        d.init = true;
+    }
+    c.device = dev;
+    c.dstat = d.dstat;
+    c.hstat = d.hstat;
+    c.panel_rec = d.panel_rec;
+    c.panel_rec_elems = d.panel_rec_elems;
+    c.rowsrc = d.rowsrc;
+    c.rowsrc_elems = d.rowsrc_elems;
+    c.num_cu = d.num_cu;
+}
+
+static void ensure_rowsrc(Ctx &c, size_t m) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState &d = g_dev[c.device];
+    if (d.rowsrc_elems < m) {
+        if (d.rowsrc) { RL_CHECK(hipStreamSynchronize(c.stream)); RL_CHECK(hipFree(d.rowsrc)); }
+        d.rowsrc = nullptr;
+        RL_CHECK(hipMalloc(&d.rowsrc, m * sizeof(int)));
+        d.rowsrc_elems = m;
+    }
+    c.rowsrc = d.rowsrc;
+    c.rowsrc_elems = d.rowsrc_elems;
+}
+
+void *scratch(Ctx &c, int slot, size_t bytes) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState &d = g_dev[c.device];
+    if (d.slot_bytes[slot] < bytes) {
+        if (d.slot[slot]) { RL_CHECK(hipStreamSynchronize(c.stream)); RL_CHECK(hipFree(d.slot[slot])); }
+        d.slot[slot] = nullptr;
+        if (hipMalloc(&d.slot[slot], bytes) != hipSuccess) {
+            d.slot_bytes[slot] = 0;
+            launch_error(hipErrorOutOfMemory);
+            return nullptr;
+        }
+        d.slot_bytes[slot] = bytes;
+    }
+    return d.slot[slot];
+}
+
+TrsvWork trsv_work(Ctx &c, long long m, int nb, int launches) {
+    TrsvWork w;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState &d = g_dev[c.device];
+    if (d.trsv_x_rows < (size_t)m) {
+        if (d.trsv_x) { RL_CHECK(hipStreamSynchronize(c.stream)); RL_CHECK(hipFree(d.trsv_x)); }
+        d.trsv_x = nullptr;
+        if (hipMalloc(&d.trsv_x, (size_t)m * 8 * sizeof(double)) != hipSuccess) {
+            d.trsv_x_rows = 0;
+            launch_error(hipErrorOutOfMemory);
+            return w;
+        }
+        d.trsv_x_rows = (size_t)m;
+    }
+    if (d.trsv_ready_n < nb) {
+        if (d.trsv_ready) { RL_CHECK(hipStreamSynchronize(c.stream)); RL_CHECK(hipFree(d.trsv_ready)); }
+        d.trsv_ready = nullptr;
+        if (hipMalloc(&d.trsv_ready, (size_t)nb * sizeof(int)) != hipSuccess) {
+            d.trsv_ready_n = 0;
+            launch_error(hipErrorOutOfMemory);
+            return w;
+        }
+        // epochs start at 1, so a fresh array (all 0) reads as "not ready"
+        hipLaunchKernelGGL(fill_int_k, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, c.stream, d.trsv_ready,
+                           (long long)nb, 0);
+        d.trsv_ready_n = nb;
+    }
+    if (!d.trsv_ticket) {
+        RL_CHECK(hipMalloc(&d.trsv_ticket, sizeof(unsigned long long)));
+        hipLaunchKernelGGL(zero_u64_one_k, dim3(1), dim3(64), 0, c.stream, d.trsv_ticket);
+        d.trsv_tickets = 0;
+    }
+    w.xbuf = d.trsv_x;
+    w.ready = d.trsv_ready;
+    w.ticket = d.trsv_ticket;
+    w.ticket_base = d.trsv_tickets;
+    w.epoch = d.trsv_epoch + 1;
+    d.trsv_tickets += (unsigned long long)nb * (unsigned long long)launches;
+    d.trsv_epoch += launches;
+    return w;
+}
+
+void trace_begin(Ctx &c, int kind) {
+    (void)kind;
+    if (!c.trace || c.plan) return;
+    if (t_evused + 2 > t_evpool.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            RL_CHECK(hipEventCreate(&e));
+            t_evpool.push_back(e);
+        }
+    }
+    RL_CHECK(hipEventRecord(t_evpool[t_evused], c.stream));
+}
+
+void trace_end(Ctx &c, int kind, double flops, double bytes) {
+    if (!c.trace || c.plan) return;
+    hipEvent_t e0 = t_evpool[t_evused], e1 = t_evpool[t_evused + 1];
+    RL_CHECK(hipEventRecord(e1, c.stream));
+    t_evused += 2;
+    t_trace.push_back(TraceRec{kind, flops, bytes, e0, e1});
+}
+
+// Begin / end of one library call.
+static bool call_begin(Ctx &c, bool abort_on_info) {
+    t_err = 0;
+    ensure_device(c);
+    if (t_err) return false;
+    c.abort_on_info = abort_on_info;
+    c.barrier_base = 0;
+    c.level = 0;
+    hipLaunchKernelGGL(reset_status_k, dim3(1), dim3(64), 0, c.stream, c.dstat);
+    RL_CHECK(hipGetLastError());
+    return t_err == 0;
+}
+
+static int call_end(Ctx &c) {
+    if (!t_err) {
+        RL_CHECK(hipMemcpyAsync(c.hstat, c.dstat, sizeof(DevStatus), hipMemcpyDeviceToHost, c.stream));
+        RL_CHECK(hipStreamSynchronize(c.stream));
+    }
+    if (t_err) return -1000 - t_err;
+    if (c.hstat->error) return -2000 - c.hstat->error;
+    return c.hstat->info;
+}
+
+static inline bool is(char a, char b) { return a == b || a == (char)(b + ('a' - 'A')); }
+
+}  // namespace rl
+
+using namespace rl;
+
+extern "C" {
+
+int relapack_version(void) { return 1; }
+
+int relapack_set_stream(void *stream) {
+    ctx().stream = (hipStream_t)stream;
+    return 0;
+}
+
+void *relapack_get_stream(void) { return (void *)ctx().stream; }
+
+void relapack_finalize(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (int i = 0; i < kMaxDev; ++i) {
+        DevState &d = g_dev[i];
+        if (!d.init) continue;
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(i);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(d.dstat);
+        (void)hipHostFree(d.hstat);
+        (void)hipFree(d.panel_rec);
+        if (d.rowsrc) (void)hipFree(d.rowsrc);
+        if (d.trsv_x) (void)hipFree(d.trsv_x);
+        if (d.trsv_ready) (void)hipFree(d.trsv_ready);
+        if (d.trsv_ticket) (void)hipFree(d.trsv_ticket);
+        for (int s = 0; s < kScratchSlots; ++s)
+            if (d.slot[s]) (void)hipFree(d.slot[s]);
+        d = DevState();
+        (void)hipSetDevice(cur);
+    }
+}
+
+void relapack_dpotrf(char uplo, int n, double *A, int lda, int *info) {
+    if (!info) return;
+    if (!is(uplo, 'L') && !is(uplo, 'U')) { *info = -1; return; }
+    if (n < 0) { *info = -2; return; }
+    if (lda < (n > 1 ? n : 1)) { *info = -4; return; }
+    *info = 0;
+    if (n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, true)) { *info = call_end(c); return; }
+    potrf_rec<double>(c, Mfma::F64, is(uplo, 'L') ? 'L' : 'U', n, A, lda, 0);
+    *info = call_end(c);
+}
+
+void relapack_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info) {
+    if (!info) return;
+    if (m < 0) { *info = -1; return; }
+    if (n < 0) { *info = -2; return; }
+    if (lda < (m > 1 ? m : 1)) { *info = -4; return; }
+    *info = 0;
+    if (m == 0 || n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    ensure_rowsrc(c, (size_t)m);
+    getrf_top<double>(c, Mfma::F64, m, n, A, lda, ipiv);
+    *info = call_end(c);
+}
+
+void relapack_dpotrs(char uplo, int n, int nrhs, const double *A, int lda, double *B, int ldb,
+                     int *info) {
+    if (!info) return;
+    if (!is(uplo, 'L') && !is(uplo, 'U')) { *info = -1; return; }
+    if (n < 0) { *info = -2; return; }
+    if (nrhs < 0) { *info = -3; return; }
+    if (lda < (n > 1 ? n : 1)) { *info = -5; return; }
+    if (ldb < (n > 1 ? n : 1)) { *info = -7; return; }
+    *info = 0;
+    if (n == 0 || nrhs == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    if (is(uplo, 'L')) {
+        trsm<double, double>(c, Mfma::F64, 'L', 'L', 'N', 'N', n, nrhs, A, lda, B, ldb);
+        trsm<double, double>(c, Mfma::F64, 'L', 'L', 'T', 'N', n, nrhs, A, lda, B, ldb);
+    } else {
+        trsm<double, double>(c, Mfma::F64, 'L', 'U', 'T', 'N', n, nrhs, A, lda, B, ldb);
+        trsm<double, double>(c, Mfma::F64, 'L', 'U', 'N', 'N', n, nrhs, A, lda, B, ldb);
+    }
+    *info = call_end(c);
+}
+
+void relapack_dgetrs(char trans, int n, int nrhs, const double *A, int lda, const int *ipiv, double *B,
+                     int ldb, int *info) {
+    if (!info) return;
+    if (!is(trans, 'N') && !is(trans, 'T') && !is(trans, 'C')) { *info = -1; return; }
+    if (n < 0) { *info = -2; return; }
+    if (nrhs < 0) { *info = -3; return; }
+    if (lda < (n > 1 ? n : 1)) { *info = -5; return; }
+    if (ldb < (n > 1 ? n : 1)) { *info = -8; return; }
+    *info = 0;
+    if (n == 0 || nrhs == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    if (is(trans, 'N')) {
+        laswp_rows<double>(c, nrhs, B, ldb, ipiv, 0, n, false);
+        trsm<double, double>(c, Mfma::F64, 'L', 'L', 'N', 'U', n, nrhs, A, lda, B, ldb);
+        trsm<double, double>(c, Mfma::F64, 'L', 'U', 'N', 'N', n, nrhs, A, lda, B, ldb);
+    } else {
+        trsm<double, double>(c, Mfma::F64, 'L', 'U', 'T', 'N', n, nrhs, A, lda, B, ldb);
+        trsm<double, double>(c, Mfma::F64, 'L', 'L', 'T', 'U', n, nrhs, A, lda, B, ldb);
+        laswp_rows<double>(c, nrhs, B, ldb, ipiv, 0, n, true);
+    }
+    *info = call_end(c);
+}
+
+void relapack_dgemm(char ta, char tb, int m, int n, int k, double alpha, const double *A, int lda,
+                    const double *B, int ldb, double beta, double *C, int ldc, int *info) {
+    if (!info) return;
+    const bool tra = is(ta, 'T') || is(ta, 'C'), trb = is(tb, 'T') || is(tb, 'C');
+    if (!tra && !is(ta, 'N')) { *info = -1; return; }
+    if (!trb && !is(tb, 'N')) { *info = -2; return; }
+    if (m < 0) { *info = -3; return; }
+    if (n < 0) { *info = -4; return; }
+    if (k < 0) { *info = -5; return; }
+    const int nrowa = tra ? k : m, nrowb = trb ? n : k;
+    if (lda < (nrowa > 1 ? nrowa : 1)) { *info = -8; return; }
+    if (ldb < (nrowb > 1 ? nrowb : 1)) { *info = -10; return; }
+    if (ldc < (m > 1 ? m : 1)) { *info = -13; return; }
+    *info = 0;
+    if (m == 0 || n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    gemm<double, double, double>(c, Mfma::F64, tra ? 'T' : 'N', trb ? 'T' : 'N', 0, m, n, k, alpha, A,
+                                 lda, B, ldb, beta, C, ldc);
+    *info = call_end(c);
+}
+
+void relapack_dsyrk(char uplo, char trans, int n, int k, double alpha, const double *A, int lda,
+                    double beta, double *C, int ldc, int *info) {
+    if (!info) return;
+    if (!is(uplo, 'L') && !is(uplo, 'U')) { *info = -1; return; }
+    const bool tr = is(trans, 'T') || is(trans, 'C');
+    if (!tr && !is(trans, 'N')) { *info = -2; return; }
+    if (n < 0) { *info = -3; return; }
+    if (k < 0) { *info = -4; return; }
+    const int nrowa = tr ? k : n;
+    if (lda < (nrowa > 1 ? nrowa : 1)) { *info = -7; return; }
+    if (ldc < (n > 1 ? n : 1)) { *info = -10; return; }
+    *info = 0;
+    if (n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    const char tri = is(uplo, 'L') ? 'L' : 'U';
+    // C = beta*C + alpha*op(A)*op(A)ᵀ; the kernel covers lower tiles with N·T
+    // and upper tiles with T·N, so map the four cases onto those two.
+    if (tri == 'L' && !tr)
+        gemm<double, double, double>(c, Mfma::F64, 'N', 'T', 'L', n, n, k, alpha, A, lda, A, lda, beta, C, ldc);
+    else if (tri == 'U' && tr)
+        gemm<double, double, double>(c, Mfma::F64, 'T', 'N', 'U', n, n, k, alpha, A, lda, A, lda, beta, C, ldc);
+    else if (tri == 'L' && tr)
+        gemm<double, double, double>(c, Mfma::F64, 'T', 'N', 'L', n, n, k, alpha, A, lda, A, lda, beta, C, ldc);
+    else
+        gemm<double, double, double>(c, Mfma::F64, 'N', 'T', 'U', n, n, k, alpha, A, lda, A, lda, beta, C, ldc);
+    *info = call_end(c);
+}
+
+void relapack_dtrsm(char side, char uplo, char transa, char diag, int m, int n, const double *A,
+                    int lda, double *B, int ldb, int *info) {
+    if (!info) return;
+    if (!is(side, 'L') && !is(side, 'R')) { *info = -1; return; }
+    if (!is(uplo, 'L') && !is(uplo, 'U')) { *info = -2; return; }
+    if (!is(transa, 'N') && !is(transa, 'T') && !is(transa, 'C')) { *info = -3; return; }
+    if (!is(diag, 'N') && !is(diag, 'U')) { *info = -4; return; }
+    if (m < 0) { *info = -5; return; }
+    if (n < 0) { *info = -6; return; }
+    const int nt = is(side, 'L') ? m : n;
+    if (lda < (nt > 1 ? nt : 1)) { *info = -8; return; }
+    if (ldb < (m > 1 ? m : 1)) { *info = -10; return; }
+    *info = 0;
+    if (m == 0 || n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    trsm<double, double>(c, Mfma::F64, is(side, 'L') ? 'L' : 'R', is(uplo, 'L') ? 'L' : 'U',
+                         is(transa, 'N') ? 'N' : 'T', is(diag, 'U') ? 'U' : 'N', m, n, A, lda, B, ldb);
+    *info = call_end(c);
+}
+
+// ---- mixed precision ------------------------------------------------------------
+
+static bool prec_ok(int prec) { return prec == 32 || prec == 16 || prec == 'b' || prec == 'B'; }
+static Mfma prec_to_mode(int prec) {
+    return prec == 16 ? Mfma::F16 : (prec == 32 ? Mfma::F32 : Mfma::BF16);
+}
+
+void relapack_dposv_mixed(char uplo, int n, int nrhs, const double *A, int lda, const double *B, int ldb,
+                          double *X, int ldx, int prec, int *iter, double *berr, int *info) {
+    if (!info) return;
+    if (!is(uplo, 'L') && !is(uplo, 'U')) { *info = -1; return; }
+    if (n < 0) { *info = -2; return; }
+    if (nrhs < 0) { *info = -3; return; }
+    if (lda < (n > 1 ? n : 1)) { *info = -5; return; }
+    if (ldb < (n > 1 ? n : 1)) { *info = -7; return; }
+    if (ldx < (n > 1 ? n : 1)) { *info = -9; return; }
+    if (!prec_ok(prec)) { *info = -10; return; }
+    *info = 0;
+    if (iter) *iter = 0;
+    if (berr) *berr = 0.0;
+    if (n == 0 || nrhs == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    int it = 0;
+    double be = 0.0;
+    const int r = mixed_solve(c, true, is(uplo, 'L') ? 'L' : 'U', n, nrhs, A, lda, nullptr, B, ldb, X, ldx,
+                              prec, &it, &be);
+    const int e = call_end(c);
+    *info = e < 0 ? e : r;
+    if (iter) *iter = it;
+    if (berr) *berr = be;
+}
+
+void relapack_dgesv_mixed(int n, int nrhs, const double *A, int lda, int *ipiv, const double *B, int ldb,
+                          double *X, int ldx, int prec, int *iter, double *berr, int *info) {
+    if (!info) return;
+    if (n < 0) { *info = -1; return; }
+    if (nrhs < 0) { *info = -2; return; }
+    if (lda < (n > 1 ? n : 1)) { *info = -4; return; }
+    if (ldb < (n > 1 ? n : 1)) { *info = -7; return; }
+    if (ldx < (n > 1 ? n : 1)) { *info = -9; return; }
+    if (!prec_ok(prec)) { *info = -10; return; }
+    *info = 0;
+    if (iter) *iter = 0;
+    if (berr) *berr = 0.0;
+    if (n == 0 || nrhs == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    ensure_rowsrc(c, (size_t)n);
+    int it = 0;
+    double be = 0.0;
+    const int r = mixed_solve(c, false, 'N', n, nrhs, A, lda, ipiv, B, ldb, X, ldx, prec, &it, &be);
+    const int e = call_end(c);
+    *info = e < 0 ? e : r;
+    if (iter) *iter = it;
+    if (berr) *berr = be;
+}
+
+void relapack_scale_spd_f32(char uplo, int n, const double *A, int lda, double *d, float *S, int lds,
+                            int *info) {
+    if (!info) return;
+    if (!is(uplo, 'L') && !is(uplo, 'U')) { *info = -1; return; }
+    if (n < 0) { *info = -2; return; }
+    if (lda < (n > 1 ? n : 1)) { *info = -4; return; }
+    if (lds < (n > 1 ? n : 1)) { *info = -7; return; }
+    *info = 0;
+    if (n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    scale_spd_f32(c, is(uplo, 'L') ? 'L' : 'U', n, A, lda, d, S, lds);
+    *info = call_end(c);
+}
+
+void relapack_scale_ge_f32(int n, const double *A, int lda, double *r, double *cs, float *S, int lds,
+                           int *info) {
+    if (!info) return;
+    if (n < 0) { *info = -1; return; }
+    if (lda < (n > 1 ? n : 1)) { *info = -3; return; }
+    if (lds < (n > 1 ? n : 1)) { *info = -7; return; }
+    *info = 0;
+    if (n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    scale_ge_f32(c, n, A, lda, r, cs, S, lds);
+    *info = call_end(c);
+}
+
+void relapack_spotrf_lp(char uplo, int n, float *A, int lda, int prec, int *info) {
+    if (!info) return;
+    if (!is(uplo, 'L') && !is(uplo, 'U')) { *info = -1; return; }
+    if (n < 0) { *info = -2; return; }
+    if (lda < (n > 1 ? n : 1)) { *info = -4; return; }
+    if (!prec_ok(prec)) { *info = -5; return; }
+    *info = 0;
+    if (n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, true)) { *info = call_end(c); return; }
+    potrf_rec<float>(c, prec_to_mode(prec), is(uplo, 'L') ? 'L' : 'U', n, A, lda, 0);
+    *info = call_end(c);
+}
+
+void relapack_sgetrf_lp(int m, int n, float *A, int lda, int *ipiv, int prec, int *info) {
+    if (!info) return;
+    if (m < 0) { *info = -1; return; }
+    if (n < 0) { *info = -2; return; }
+    if (lda < (m > 1 ? m : 1)) { *info = -4; return; }
+    if (!prec_ok(prec)) { *info = -6; return; }
+    *info = 0;
+    if (m == 0 || n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    ensure_rowsrc(c, (size_t)m);
+    getrf_top<float>(c, prec_to_mode(prec), m, n, A, lda, ipiv);
+    *info = call_end(c);
+}
+
+// ---- tracing ----------------------------------------------------------------
+
+void relapack_trace_enable(int on) {
+    Ctx &c = ctx();
+    c.trace = on != 0;
+    t_trace.clear();
+    t_evused = 0;
+}
+
+// Per kernel family k in [0, cap): out[4k..4k+3] = {launches, total ms, flops, bytes}.
+// Synchronizes the library stream. Returns the number of families written.
+int relapack_trace_collect(double *out, int cap) {
+    Ctx &c = ctx();
+    if (hipStreamSynchronize(c.stream) != hipSuccess) return -1;
+    for (int i = 0; i < 4 * cap; ++i) out[i] = 0.0;
+    for (auto &r : t_trace) {
+        if (r.kind < 0 || r.kind >= cap) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) ms = 0.f;
+        out[4 * r.kind + 0] += 1.0;
+        out[4 * r.kind + 1] += ms;
+        out[4 * r.kind + 2] += r.flops;
+        out[4 * r.kind + 3] += r.bytes;
+    }
+    t_trace.clear();
+    t_evused = 0;
+    return cap;
+}
+
+// ---- plan mode: the call sequence of one factorization, without launching ---
+
+// routine: "potrf_L", "potrf_U" or "getrf". Writes up to cap records of
+// {kind, level, m, n, k} (5 int64 each) into rec; returns the total count.
+long long relapack_plan(const char *routine, long long m, long long n, int leaf, long long *rec,
+                        long long cap) {
+    Ctx &c = ctx();
+    std::vector<PlanRec> out;
+    Ctx saved = c;
+    c.plan = true;
+    c.plan_out = &out;
+    c.plan_leaf = leaf;
+    c.level = 0;
+    c.abort_on_info = false;
+    std::string r = routine ? routine : "";
+    if (r == "potrf_L") potrf_rec<double>(c, Mfma::F64, 'L', n, nullptr, n, 0);
+    else if (r == "potrf_U") potrf_rec<double>(c, Mfma::F64, 'U', n, nullptr, n, 0);
+    else if (r == "getrf") getrf_top<double>(c, Mfma::F64, m, n, nullptr, m, nullptr);
+    else { c = saved; return -1; }
+    c = saved;
+    for (long long i = 0; i < (long long)out.size() && i < cap; ++i) {
+        rec[5 * i + 0] = out[i].kind;
+        rec[5 * i + 1] = out[i].level;
+        rec[5 * i + 2] = out[i].m;
+        rec[5 * i + 3] = out[i].n;
+        rec[5 * i + 4] = out[i].k;
+    }
+    return (long long)out.size();
+}
+
+long long relapack_split(long long n) { return split_size(n); }
+
+}  // extern "C"

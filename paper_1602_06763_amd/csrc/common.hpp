@@ -1,0 +1,170 @@
+// Shared declarations of the recursive-factorization library (gfx950 only).
+//
+// Layout conventions used everywhere: column-major storage with a leading
+// dimension (LAPACK), 64-bit index arithmetic, 1-based pivot indices.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace rl {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bh8 __attribute__((ext_vector_type(8)));
+
+// Arithmetic used by the matrix cores in the low-precision factorization.
+enum class Mfma : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3 };
+
+// Compile-time recursion constants. The leaf sizes are fixed by on-chip
+// capacity (a 64×64 FP64 block is 32 KiB of LDS), not tuned per size.
+constexpr int kSplitQuantum = 64;   // halves are multiples of this where possible
+constexpr int kCholLeaf = 64;       // potf2 leaf: n <= kCholLeaf
+constexpr int kTrsmLeaf = 64;       // triangular solve leaf: triangle <= kTrsmLeaf
+constexpr int kLuLeaf = 32;         // getf2 panel width
+constexpr int kPanelMaxWG = 256;    // cooperative panel: at most one workgroup per CU
+constexpr int kTrsvMaxRhs = 32;     // left-side solves with at most this many right-hand sides
+                                    // take the single-launch blocked solve
+
+// Per-call status record shared by every kernel of one library call.
+struct DevStatus {
+    int info;       // LAPACK info (first failing column, 1-based), 0 = fine
+    int error;      // internal failure (e.g. a bounded wait that expired)
+    unsigned int barrier;  // cooperative-panel arrival counter
+    int pad;
+};
+
+// One recorded kernel call (plan mode and the per-family timers).
+struct PlanRec {
+    int kind;   // see PlanKind
+    int level;  // recursion depth (0 = top)
+    long long m, n, k;
+};
+
+enum PlanKind : int {
+    PK_POTF2 = 1, PK_TRSM_LEAF = 2, PK_GEMM = 3, PK_SYRK = 4, PK_GETF2 = 5, PK_LASWP = 6,
+    PK_CONVERT = 7, PK_RESID = 8, PK_OTHER = 9, PK_GEMM_LP = 10, PK_SYRK_LP = 11
+};
+
+// Per-thread library state: stream, plan recording, tracing.
+struct Ctx {
+    hipStream_t stream = nullptr;
+    int device = -1;
+    DevStatus *dstat = nullptr;      // device status block (per device)
+    DevStatus *hstat = nullptr;      // pinned host mirror
+    // cooperative panel scratch (per device)
+    double *panel_rec = nullptr;
+    size_t panel_rec_elems = 0;
+    int *rowsrc = nullptr;
+    size_t rowsrc_elems = 0;
+    // plan mode: record instead of launch
+    bool plan = false;
+    std::vector<PlanRec> *plan_out = nullptr;
+    int level = 0;
+    int plan_leaf = 0;               // override of leaf sizes in plan mode (0 = defaults)
+    // potrf: every kernel returns at once after a leaf has reported info != 0
+    bool abort_on_info = false;
+    // tracing: per-kernel-family event timing on the library stream
+    bool trace = false;
+    unsigned int barrier_base = 0;   // running target of the panel arrival counter
+    int num_cu = 256;
+};
+
+Ctx &ctx();
+void ensure_device(Ctx &c);
+void *scratch(Ctx &c, int slot, size_t bytes);   // grow-only per-device workspace
+
+// Tracing hook: kernels are bracketed by events when tracing is on.
+void trace_begin(Ctx &c, int kind);
+void trace_end(Ctx &c, int kind, double flops, double bytes);
+
+inline bool plan_record(Ctx &c, int kind, long long m, long long n, long long k) {
+    if (!c.plan) return false;
+    if (c.plan_out) c.plan_out->push_back(PlanRec{kind, c.level, m, n, k});
+    return true;
+}
+
+// ---- building blocks (host launchers) --------------------------------------
+
+// C := beta*C + alpha*op(A)*op(B), with op = identity ('N') or transpose ('T').
+// TA/TB/TC: storage types in HBM; mode: matrix-core arithmetic. tri = 0: full
+// C; 'L'/'U': only the lower/upper triangle of a square C is read or written.
+template <typename TA, typename TB, typename TC>
+void gemm(Ctx &c, Mfma mode, char ta, char tb, char tri, long long m, long long n, long long k,
+          double alpha, const TA *A, long long lda, const TB *B, long long ldb, double beta, TC *C,
+          long long ldc);
+
+// Triangular solve with many right-hand sides, recursive down to the leaf:
+// side 'L': op(T)·X = B, side 'R': X·op(T) = B; X overwrites B (m×n).
+// TT: triangle storage type, TB: right-hand-side storage type.
+template <typename TT, typename TB>
+void trsm(Ctx &c, Mfma mode, char side, char uplo, char trans, char diag, long long m, long long n,
+          const TT *T, long long ldt, TB *B, long long ldb);
+
+// Cholesky / LU recursion (typed over the storage type of the matrix).
+template <typename T>
+void potrf_rec(Ctx &c, Mfma mode, char uplo, long long n, T *A, long long lda, long long off);
+template <typename T>
+void getrf_top(Ctx &c, Mfma mode, long long m, long long n, T *A, long long lda, int *ipiv);
+
+// Leaf kernels.
+template <typename T>
+void potf2(Ctx &c, char uplo, int n, T *A, long long lda, long long off);
+template <typename TT, typename TB>
+void trsm_leaf(Ctx &c, bool lower_eff, bool unit, int t, const TT *T, long long ti, long long tj,
+               long long nvec, TB *B, long long se, long long sr);
+template <typename T>
+void getf2_panel(Ctx &c, long long m, int w, T *A, long long lda, long long off, int *ipiv);
+template <typename T>
+void laswp_leaf(Ctx &c, long long ncols_total, T *A, long long lda, long long k0, int w, long long m,
+                const int *ipiv, long long skip_lo, long long skip_hi);
+template <typename T>
+void laswp_rows(Ctx &c, long long n, T *B, long long ldb, const int *ipiv, long long k1, long long k2,
+                bool reverse);
+
+// Mixed precision helpers.
+void scale_spd_f32(Ctx &c, char uplo, long long n, const double *A, long long lda, double *d,
+                   float *S, long long lds);
+void scale_ge_f32(Ctx &c, long long n, const double *A, long long lda, double *r, double *cs,
+                  float *S, long long lds);
+
+int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const double *A, long long lda,
+                int *ipiv_out, const double *B, long long ldb, double *X, long long ldx, int prec, int *iter,
+                double *berr);
+
+// Split rule: halves are multiples of kSplitQuantum where possible.
+inline long long split_size(long long n, long long quantum = kSplitQuantum) {
+    if (n >= 2 * quantum) {
+        long long n1 = ((n / 2 + quantum / 2) / quantum) * quantum;
+        if (n1 < quantum) n1 = quantum;
+        if (n1 >= n) n1 = n - quantum;
+        return n1;
+    }
+    return n / 2;
+}
+
+int launch_error(hipError_t e);
+
+// Workspace of the single-launch triangular solve: ticket counter, per-block
+// ready flags (compared against a per-launch epoch) and published solutions.
+struct TrsvWork {
+    double *xbuf = nullptr;
+    int *ready = nullptr;
+    unsigned long long *ticket = nullptr;
+    unsigned long long ticket_base = 0;
+    int epoch = 0;
+};
+// Reserves ticket and epoch ranges for ceil(nrhs/8) launches of nb blocks.
+TrsvWork trsv_work(Ctx &c, long long m, int nb, int launches = 4);  // records a HIP failure in the calling thread's state
+
+}  // namespace rl
+
+#define RL_CHECK(expr)                                        \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) { rl::launch_error(_e); }       \
+    } while (0)

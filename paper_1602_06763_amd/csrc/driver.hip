@@ -1,0 +1,96 @@
+// Recursion driver: the recursive Cholesky and LU of the ReLAPACK collection,
+// expressed as a size-based split with no block-size tuning.
+//
+// The recursive algorithm is the blocked algorithm with block size n/2, the
+// unblocked kernel call replaced by a recursive call (Sec. 3, first paragraph
+// and footnote); halves are multiples of a fixed quantum where possible (the
+// footnote on alignment in Sec. 3); below the crossover size the unblocked
+// kernel runs (Sec. 3, paragraph on c). Cholesky and LU are the routines
+// xpotrf and xgetrf of Sec. 5.
+#include "common.hpp"
+
+namespace rl {
+
+// ---------------------------------------------------------------------------
+// Cholesky, lower: A = L·Lᵀ.  potrf(A11); A21 := A21·L11⁻ᵀ; A22 -= A21·A21ᵀ;
+// potrf(A22).  Upper: A = Uᵀ·U.  potrf(A11); A12 := U11⁻ᵀ·A12;
+// A22 -= A12ᵀ·A12; potrf(A22).
+// ---------------------------------------------------------------------------
+template <typename T>
+void potrf_rec(Ctx &c, Mfma mode, char uplo, long long n, T *A, long long lda, long long off) {
+    const int leaf = c.plan && c.plan_leaf > 0 ? c.plan_leaf : kCholLeaf;
+    if (n <= leaf) {
+        potf2<T>(c, uplo, (int)n, A, lda, off);
+        return;
+    }
+    const long long n1 = split_size(n), n2 = n - n1;
+    const bool lower = (uplo == 'L' || uplo == 'l');
+    T *A11 = A, *A22 = A + n1 + n1 * lda;
+    c.level++;
+    potrf_rec<T>(c, mode, uplo, n1, A11, lda, off);
+    c.level--;
+    if (lower) {
+        T *A21 = A + n1;
+        trsm<T, T>(c, mode, 'R', 'L', 'T', 'N', n2, n1, A11, lda, A21, lda);
+        gemm<T, T, T>(c, mode, 'N', 'T', 'L', n2, n2, n1, -1.0, A21, lda, A21, lda, 1.0, A22, lda);
+    } else {
+        T *A12 = A + n1 * lda;
+        trsm<T, T>(c, mode, 'L', 'U', 'T', 'N', n1, n2, A11, lda, A12, lda);
+        gemm<T, T, T>(c, mode, 'T', 'N', 'U', n2, n2, n1, -1.0, A12, lda, A12, lda, 1.0, A22, lda);
+    }
+    c.level++;
+    potrf_rec<T>(c, mode, uplo, n2, A22, lda, off + n1);
+    c.level--;
+}
+
+template void potrf_rec<double>(Ctx &, Mfma, char, long long, double *, long long, long long);
+template void potrf_rec<float>(Ctx &, Mfma, char, long long, float *, long long, long long);
+
+// ---------------------------------------------------------------------------
+// LU with partial pivoting on the columns [c0, c0+w) of an m×ncols matrix,
+// rows [c0, m).  getrf(left half); A12 := L11⁻¹·A12; A22 -= A21·A12;
+// getrf(right half).  Each leaf panel applies its interchanges to all other
+// columns at once (the row swaps of the left-hand and right-hand blocks that
+// the recursion performs after each half); every column receives exactly the
+// interchanges it would have received, in the same order, so the result is
+// the same.
+// ---------------------------------------------------------------------------
+template <typename T>
+static void getrf_rec(Ctx &c, Mfma mode, long long m, long long ncols, T *A, long long lda, int *ipiv,
+                      long long c0, long long w) {
+    const int leaf = c.plan && c.plan_leaf > 0 ? c.plan_leaf : kLuLeaf;
+    if (w <= leaf) {
+        getf2_panel<T>(c, m, (int)w, A, lda, c0, ipiv);
+        laswp_leaf<T>(c, ncols, A, lda, c0, (int)w, m, ipiv, c0, c0 + w);
+        return;
+    }
+    const long long w1 = split_size(w), w2 = w - w1;
+    c.level++;
+    getrf_rec<T>(c, mode, m, ncols, A, lda, ipiv, c0, w1);
+    c.level--;
+    T *A11 = A + c0 + c0 * lda;
+    T *A12 = A + c0 + (c0 + w1) * lda;
+    T *A21 = A + (c0 + w1) + c0 * lda;
+    T *A22 = A + (c0 + w1) + (c0 + w1) * lda;
+    trsm<T, T>(c, mode, 'L', 'L', 'N', 'U', w1, w2, A11, lda, A12, lda);
+    gemm<T, T, T>(c, mode, 'N', 'N', 0, m - c0 - w1, w2, w1, -1.0, A21, lda, A12, lda, 1.0, A22, lda);
+    c.level++;
+    getrf_rec<T>(c, mode, m, ncols, A, lda, ipiv, c0 + w1, w2);
+    c.level--;
+}
+
+template <typename T>
+void getrf_top(Ctx &c, Mfma mode, long long m, long long n, T *A, long long lda, int *ipiv) {
+    const long long mn = m < n ? m : n;
+    if (mn <= 0) return;
+    getrf_rec<T>(c, mode, m, n, A, lda, ipiv, 0, mn);
+    if (n > m) {
+        // U12 = L11⁻¹·(P·A12) for the columns beyond the square part
+        trsm<T, T>(c, mode, 'L', 'L', 'N', 'U', m, n - m, A, lda, A + m * lda, lda);
+    }
+}
+
+template void getrf_top<double>(Ctx &, Mfma, long long, long long, double *, long long, int *);
+template void getrf_top<float>(Ctx &, Mfma, long long, long long, float *, long long, int *);
+
+}  // namespace rl

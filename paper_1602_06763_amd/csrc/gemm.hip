@@ -1,0 +1,516 @@
+// Matrix-core GEMM / SYRK for the trailing updates of the recursion.
+//
+// C := beta*C + alpha*op(A)*op(B). These carry almost all of the flops of a
+// recursive factorization: the paper's analysis (Sec. 3, Fig.
+// recursive_breakdown and the flop-share equation beside it) shows that the
+// BLAS-3 calls of the top recursion level alone hold 3/4 of the work and the
+// BLAS-3 calls of all levels more than 99.6 % of it. Cholesky's trailing update
+// A22 -= A21*A21ᵀ is the triangular ("tri") instance of the same kernel: only
+// the tiles of one triangle are launched and the diagonal tiles are masked.
+//
+// Design (gfx950):
+//  * 256 threads = 4 waves in a 2×2 arrangement; the workgroup tile is BM×BN
+//    (128×128 or 64×64), each wave owns (BM/2)×(BN/2) as a grid of 16×16
+//    matrix-core blocks; BK = 16 is staged through LDS, double-buffered, one
+//    barrier per K step. Operands are stored in LDS k-major ([k][m]) so that
+//    the 16 lanes of a matrix-core row group read 16 consecutive elements.
+//  * The K loop prefetches the next tile from HBM into registers while the
+//    matrix cores work on the current one.
+//  * XCD-aware launch: workgroup b runs on XCD b % 8; logical tiles are dealt
+//    out so that each XCD gets a contiguous run of them, and tiles are ordered
+//    in groups of 8 tile-rows so that neighbours share A panels in that XCD's L2.
+//  * FP64 (v_mfma_f64_16x16x4f64) and FP32 (v_mfma_f32_16x16x4f32) operands;
+//    the operand type in LDS (TL) may differ from the storage types, e.g. FP32
+//    factors multiplied in FP64 during iterative refinement.
+#include "common.hpp"
+
+namespace rl {
+
+template <typename TL>
+struct MfmaK1;
+
+template <>
+struct MfmaK1<double> {
+    typedef d4 acc_t;
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // FP64 16×16×4: element v of lane l is D[l/16 + 4v][l%16]
+    static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+
+template <>
+struct MfmaK1<float> {
+    typedef f4 acc_t;
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // FP32 16×16×4: element v of lane l is D[4*(l/16) + v][l%16]
+    static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+template <typename TA, typename TB, typename TC>
+struct GemmArgs {
+    long long m, n, k;
+    double alpha, beta;
+    const TA *A;
+    long long lda;
+    const TB *B;
+    long long ldb;
+    TC *C;
+    long long ldc;
+    int tiles_m, tiles_n, ntiles;
+    const int *abort;  // non-null: skip all work when *abort != 0
+};
+
+// Map the hardware workgroup id to a logical tile id, giving each of the 8 XCDs
+// a contiguous range of logical tiles (the grid is padded to a multiple of 8).
+__device__ __forceinline__ int xcd_logical(int bid, int grid) {
+    const int per = grid >> 3;
+    return (bid & 7) * per + (bid >> 3);
+}
+
+template <typename TL, typename TA, typename TB, typename TC, bool TRA, bool TRB, int TRI, int BM,
+          int BN>
+__global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
+    constexpr int BK = 16;
+    constexpr int PAD = 1;
+    constexpr int MI = BM / 32, NI = BN / 32;
+    constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+    typedef MfmaK1<TL> Op;
+    typedef typename Op::acc_t acc_t;
+
+    if (g.abort && *g.abort) return;
+    const int tile = xcd_logical(blockIdx.x, gridDim.x);
+    if (tile >= g.ntiles) return;
+
+    int tm, tn;
+    if (TRI == 0) {
+        constexpr int GROUP = 8;
+        const int gsize = GROUP * g.tiles_n;
+        const int grp = tile / gsize;
+        const int first = grp * GROUP;
+        const int gm = min(g.tiles_m - first, GROUP);
+        const int r = tile - grp * gsize;
+        tm = first + r % gm;
+        tn = r / gm;
+    } else {
+        // row-major enumeration of the lower tile triangle: tile = tm(tm+1)/2 + tn
+        int t = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+        while ((t + 1) * (t + 2) / 2 <= tile) ++t;
+        while (t * (t + 1) / 2 > tile) --t;
+        const int u = tile - t * (t + 1) / 2;
+        if (TRI == 1) { tm = t; tn = u; }   // lower: tm >= tn
+        else { tm = u; tn = t; }            // upper: tm <= tn
+    }
+
+    const long long m0 = (long long)tm * BM, n0 = (long long)tn * BN;
+    const long long M = g.m, N = g.n, K = g.k;
+    const TA *__restrict__ A = g.A;
+    const TB *__restrict__ B = g.B;
+
+    __shared__ TL As[2][BK][BM + PAD];
+    __shared__ TL Bs[2][BK][BN + PAD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
+
+    TA ra[EA];
+    TB rb[EB];
+
+    // element coordinates of this thread's share of a K tile
+    auto a_coord = [&](int i, int &r, int &kk) {
+        if (!TRA) { r = tid % BM; kk = tid / BM + i * (256 / BM); }
+        else { kk = tid % BK; r = tid / BK + i * (256 / BK); }
+    };
+    auto b_coord = [&](int i, int &c, int &kk) {
+        if (TRB) { c = tid % BN; kk = tid / BN + i * (256 / BN); }
+        else { kk = tid % BK; c = tid / BK + i * (256 / BK); }
+    };
+
+    auto load_tiles = [&](long long k0) {
+        const bool afull = (m0 + BM <= M) && (k0 + BK <= K);
+        const bool bfull = (n0 + BN <= N) && (k0 + BK <= K);
+        if (afull) {
+#pragma unroll
+            for (int i = 0; i < EA; ++i) {
+                int r, kk;
+                a_coord(i, r, kk);
+                const long long gr = m0 + r, gk = k0 + kk;
+                ra[i] = A[TRA ? gk + gr * g.lda : gr + gk * g.lda];
+            }
+        } else {
+            // edge tile (rare in the large updates): guarded loads keep register
+            // pressure at the fast path's level
+#pragma unroll
+            for (int i = 0; i < EA; ++i) {
+                int r, kk;
+                a_coord(i, r, kk);
+                const long long gr = m0 + r, gk = k0 + kk;
+                ra[i] = (gr < M && gk < K) ? A[TRA ? gk + gr * g.lda : gr + gk * g.lda] : TA(0);
+            }
+        }
+        if (bfull) {
+#pragma unroll
+            for (int i = 0; i < EB; ++i) {
+                int c, kk;
+                b_coord(i, c, kk);
+                const long long gc = n0 + c, gk = k0 + kk;
+                rb[i] = B[TRB ? gc + gk * g.ldb : gk + gc * g.ldb];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < EB; ++i) {
+                int c, kk;
+                b_coord(i, c, kk);
+                const long long gc = n0 + c, gk = k0 + kk;
+                rb[i] = (gc < N && gk < K) ? B[TRB ? gc + gk * g.ldb : gk + gc * g.ldb] : TB(0);
+            }
+        }
+    };
+    auto store_tiles = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < EA; ++i) {
+            int r, kk;
+            a_coord(i, r, kk);
+            As[buf][kk][r] = (TL)ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < EB; ++i) {
+            int c, kk;
+            b_coord(i, c, kk);
+            Bs[buf][kk][c] = (TL)rb[i];
+        }
+    };
+
+    acc_t acc[MI][NI];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+    const long long KT = (K + BK - 1) / BK;
+    if (KT > 0) {
+        load_tiles(0);
+        store_tiles(0);
+        __syncthreads();
+    }
+    for (long long kt = 0; kt < KT; ++kt) {
+        const int buf = (int)(kt & 1);
+        if (kt + 1 < KT) load_tiles((kt + 1) * BK);
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            TL a[MI], b[NI];
+#pragma unroll
+            for (int i = 0; i < MI; ++i) a[i] = As[buf][kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < NI; ++j) b[j] = Bs[buf][kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < MI; ++i)
+#pragma unroll
+                for (int j = 0; j < NI; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
+        }
+        if (kt + 1 < KT) store_tiles(buf ^ 1);
+        __syncthreads();
+    }
+
+    const double alpha = g.alpha, beta = g.beta;
+    TC *__restrict__ C = g.C;
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const long long r = m0 + wm + i * 16 + Op::row(lane, v);
+                const long long cc = n0 + wn + j * 16 + (lane & 15);
+                if (r >= M || cc >= N) continue;
+                if (TRI == 1 && r < cc) continue;
+                if (TRI == 2 && r > cc) continue;
+                TC *p = C + r + cc * g.ldc;
+                const double val = (double)acc[i][j][v];
+                if (beta == 0.0) *p = (TC)(alpha * val);
+                else *p = (TC)(alpha * val + beta * (double)(*p));
+            }
+}
+
+template <typename TL, typename TA, typename TB, typename TC, bool TRA, bool TRB, int TRI, int BM>
+static void launch_k1(Ctx &c, const GemmArgs<TA, TB, TC> &args0) {
+    GemmArgs<TA, TB, TC> a = args0;
+    a.tiles_m = (int)((a.m + BM - 1) / BM);
+    a.tiles_n = (int)((a.n + BM - 1) / BM);
+    a.ntiles = TRI ? a.tiles_m * (a.tiles_m + 1) / 2 : a.tiles_m * a.tiles_n;
+    if (a.ntiles <= 0) return;
+    const int grid = (a.ntiles + 7) / 8 * 8;
+    hipLaunchKernelGGL((gemm_k1<TL, TA, TB, TC, TRA, TRB, TRI, BM, BM>), dim3(grid), dim3(256), 0,
+                       c.stream, a);
+    RL_CHECK(hipGetLastError());
+}
+
+template <typename TL, typename TA, typename TB, typename TC, bool TRA, bool TRB, int TRI>
+static void dispatch_tile(Ctx &c, const GemmArgs<TA, TB, TC> &a) {
+    const long long big = ((a.m + 127) / 128) * ((a.n + 127) / 128) / (TRI ? 2 : 1);
+    if (big >= 2LL * c.num_cu) launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 128>(c, a);
+    else launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 64>(c, a);
+}
+
+template <typename TL, typename TA, typename TB, typename TC>
+static void dispatch(Ctx &c, char ta, char tb, char tri, const GemmArgs<TA, TB, TC> &a) {
+    const bool TA_ = (ta == 'T' || ta == 't'), TB_ = (tb == 'T' || tb == 't');
+    const int T = (tri == 'L' || tri == 'l') ? 1 : (tri == 'U' || tri == 'u') ? 2 : 0;
+#define RL_G(x, y, z)                                                         \
+    if (TA_ == x && TB_ == y && T == z) {                                     \
+        dispatch_tile<TL, TA, TB, TC, x, y, z>(c, a);                         \
+        return;                                                               \
+    }
+    RL_G(false, false, 0) RL_G(false, true, 0) RL_G(true, false, 0) RL_G(true, true, 0)
+    RL_G(false, true, 1) RL_G(true, false, 1) RL_G(false, true, 2) RL_G(true, false, 2)
+#undef RL_G
+    launch_error(hipErrorInvalidValue);
+}
+
+
+// ---------------------------------------------------------------------------
+// Half-precision operands (FP16 or BF16) with FP32 accumulation, for the
+// low-precision factorization of the mixed solvers. Storage stays FP32 (the
+// Schur complements accumulate in FP32); operands are rounded to 16 bits as
+// they are staged into LDS. v_mfma_f32_16x16x32_{f16,bf16}: each lane feeds 8
+// consecutive k of one row/column, so LDS holds tiles k-contiguous
+// ([m][k], padded) and a lane's operand is one 16-byte LDS read. The output
+// layout is D[4*(l/16) + v][l%16].
+// ---------------------------------------------------------------------------
+template <typename H>
+struct MfmaK8;
+
+template <>
+struct MfmaK8<_Float16> {
+    typedef h8 vec_t;
+    static __device__ __forceinline__ f4 mma(vec_t a, vec_t b, f4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <>
+struct MfmaK8<__bf16> {
+    typedef bh8 vec_t;
+    static __device__ __forceinline__ f4 mma(vec_t a, vec_t b, f4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename H, bool TRA, bool TRB, int TRI, int BM>
+__global__ __launch_bounds__(256) void gemm_k8(GemmArgs<float, float, float> g) {
+    constexpr int BN = BM;
+    constexpr int BK = 32;
+    constexpr int LDK = BK + 8;  // halves per LDS row (16-byte aligned rows, skewed banks)
+    constexpr int MI = BM / 32, NI = BN / 32;
+    constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+    typedef MfmaK8<H> Op;
+    typedef typename Op::vec_t vec_t;
+
+    if (g.abort && *g.abort) return;
+    const int tile = xcd_logical(blockIdx.x, gridDim.x);
+    if (tile >= g.ntiles) return;
+    int tm, tn;
+    if (TRI == 0) {
+        constexpr int GROUP = 8;
+        const int gsize = GROUP * g.tiles_n;
+        const int grp = tile / gsize;
+        const int first = grp * GROUP;
+        const int gm = min(g.tiles_m - first, GROUP);
+        const int r = tile - grp * gsize;
+        tm = first + r % gm;
+        tn = r / gm;
+    } else {
+        int t = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+        while ((t + 1) * (t + 2) / 2 <= tile) ++t;
+        while (t * (t + 1) / 2 > tile) --t;
+        const int u = tile - t * (t + 1) / 2;
+        if (TRI == 1) { tm = t; tn = u; }
+        else { tm = u; tn = t; }
+    }
+    const long long m0 = (long long)tm * BM, n0 = (long long)tn * BN;
+    const long long M = g.m, N = g.n, K = g.k;
+    const float *__restrict__ A = g.A;
+    const float *__restrict__ B = g.B;
+
+    __shared__ __attribute__((aligned(16))) H As[2][BM][LDK];
+    __shared__ __attribute__((aligned(16))) H Bs[2][BN][LDK];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
+    float ra[EA], rb[EB];
+
+    auto a_coord = [&](int i, int &r, int &kk) {
+        if (!TRA) { r = tid % BM; kk = tid / BM + i * (256 / BM); }
+        else { kk = tid % BK; r = tid / BK + i * (256 / BK); }
+    };
+    auto b_coord = [&](int i, int &c, int &kk) {
+        if (TRB) { c = tid % BN; kk = tid / BN + i * (256 / BN); }
+        else { kk = tid % BK; c = tid / BK + i * (256 / BK); }
+    };
+    auto load_tiles = [&](long long k0) {
+        const bool afull = (m0 + BM <= M) && (k0 + BK <= K);
+        const bool bfull = (n0 + BN <= N) && (k0 + BK <= K);
+#pragma unroll
+        for (int i = 0; i < EA; ++i) {
+            int r, kk;
+            a_coord(i, r, kk);
+            const long long gr = m0 + r, gk = k0 + kk;
+            const long long off = TRA ? gk + gr * g.lda : gr + gk * g.lda;
+            const bool in = afull || (gr < M && gk < K);
+            const float v = A[in ? off : 0];
+            ra[i] = in ? v : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < EB; ++i) {
+            int c, kk;
+            b_coord(i, c, kk);
+            const long long gc = n0 + c, gk = k0 + kk;
+            const long long off = TRB ? gc + gk * g.ldb : gk + gc * g.ldb;
+            const bool in = bfull || (gc < N && gk < K);
+            const float v = B[in ? off : 0];
+            rb[i] = in ? v : 0.f;
+        }
+    };
+    auto store_tiles = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < EA; ++i) {
+            int r, kk;
+            a_coord(i, r, kk);
+            As[buf][r][kk] = (H)ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < EB; ++i) {
+            int c, kk;
+            b_coord(i, c, kk);
+            Bs[buf][c][kk] = (H)rb[i];
+        }
+    };
+
+    f4 acc[MI][NI];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j) acc[i][j] = f4{0, 0, 0, 0};
+
+    const long long KT = (K + BK - 1) / BK;
+    if (KT > 0) {
+        load_tiles(0);
+        store_tiles(0);
+        __syncthreads();
+    }
+    for (long long kt = 0; kt < KT; ++kt) {
+        const int buf = (int)(kt & 1);
+        if (kt + 1 < KT) load_tiles((kt + 1) * BK);
+        const int kq = 8 * (lane >> 4);
+        vec_t a[MI], b[NI];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) a[i] = *reinterpret_cast<const vec_t *>(&As[buf][wm + i * 16 + (lane & 15)][kq]);
+#pragma unroll
+        for (int j = 0; j < NI; ++j) b[j] = *reinterpret_cast<const vec_t *>(&Bs[buf][wn + j * 16 + (lane & 15)][kq]);
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NI; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
+        if (kt + 1 < KT) store_tiles(buf ^ 1);
+        __syncthreads();
+    }
+
+    const float alpha = (float)g.alpha, beta = (float)g.beta;
+    float *__restrict__ C = g.C;
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const long long r = m0 + wm + i * 16 + 4 * (lane >> 4) + v;
+                const long long cc = n0 + wn + j * 16 + (lane & 15);
+                if (r >= M || cc >= N) continue;
+                if (TRI == 1 && r < cc) continue;
+                if (TRI == 2 && r > cc) continue;
+                float *p = C + r + cc * g.ldc;
+                *p = beta == 0.f ? alpha * acc[i][j][v] : alpha * acc[i][j][v] + beta * (*p);
+            }
+}
+
+template <typename H, bool TRA, bool TRB, int TRI, int BM>
+static void launch_k8(Ctx &c, const GemmArgs<float, float, float> &args0) {
+    GemmArgs<float, float, float> a = args0;
+    a.tiles_m = (int)((a.m + BM - 1) / BM);
+    a.tiles_n = (int)((a.n + BM - 1) / BM);
+    a.ntiles = TRI ? a.tiles_m * (a.tiles_m + 1) / 2 : a.tiles_m * a.tiles_n;
+    if (a.ntiles <= 0) return;
+    const int grid = (a.ntiles + 7) / 8 * 8;
+    hipLaunchKernelGGL((gemm_k8<H, TRA, TRB, TRI, BM>), dim3(grid), dim3(256), 0, c.stream, a);
+    RL_CHECK(hipGetLastError());
+}
+
+template <typename H>
+static void dispatch8(Ctx &c, char ta, char tb, char tri, const GemmArgs<float, float, float> &a) {
+    const bool TA_ = (ta == 'T' || ta == 't'), TB_ = (tb == 'T' || tb == 't');
+    const int T = (tri == 'L' || tri == 'l') ? 1 : (tri == 'U' || tri == 'u') ? 2 : 0;
+    const long long big = ((a.m + 127) / 128) * ((a.n + 127) / 128) / (T ? 2 : 1);
+    const bool b128 = big >= 2LL * c.num_cu;
+#define RL_G8(x, y, z)                                                                      \
+    if (TA_ == x && TB_ == y && T == z) {                                                   \
+        if (b128) launch_k8<H, x, y, z, 128>(c, a); else launch_k8<H, x, y, z, 64>(c, a);   \
+        return;                                                                             \
+    }
+    RL_G8(false, false, 0) RL_G8(false, true, 0) RL_G8(true, false, 0) RL_G8(true, true, 0)
+    RL_G8(false, true, 1) RL_G8(true, false, 1) RL_G8(false, true, 2) RL_G8(true, false, 2)
+#undef RL_G8
+    launch_error(hipErrorInvalidValue);
+}
+
+template <typename TA, typename TB, typename TC>
+static inline void dispatch_half(Ctx &, Mfma, char, char, char, const GemmArgs<TA, TB, TC> &) {
+    launch_error(hipErrorInvalidValue);  // half-precision operands need FP32 storage throughout
+}
+
+static inline void dispatch_half(Ctx &c, Mfma mode, char ta, char tb, char tri,
+                                 const GemmArgs<float, float, float> &a) {
+    if (mode == Mfma::F16) dispatch8<_Float16>(c, ta, tb, tri, a);
+    else dispatch8<__bf16>(c, ta, tb, tri, a);
+}
+
+template <typename TA, typename TB, typename TC>
+void gemm(Ctx &c, Mfma mode, char ta, char tb, char tri, long long m, long long n, long long k,
+          double alpha, const TA *A, long long lda, const TB *B, long long ldb, double beta, TC *C,
+          long long ldc) {
+    const double flops = tri ? (double)m * (double)(m + 1) * (double)k : 2.0 * m * n * k;
+    if (plan_record(c, tri ? PK_SYRK : PK_GEMM, m, n, k)) return;
+    if (m <= 0 || n <= 0) return;
+    GemmArgs<TA, TB, TC> a{};
+    a.m = m; a.n = n; a.k = k;
+    a.alpha = alpha; a.beta = beta;
+    a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc;
+    a.abort = c.dstat ? &c.dstat->info : nullptr;
+    if (!c.abort_on_info) a.abort = nullptr;
+    const int kind = mode == Mfma::F64 ? (tri ? PK_SYRK : PK_GEMM) : (tri ? PK_SYRK_LP : PK_GEMM_LP);
+    trace_begin(c, kind);
+    if (mode == Mfma::F64) dispatch<double>(c, ta, tb, tri, a);
+    else if (mode == Mfma::F32) dispatch<float>(c, ta, tb, tri, a);
+    else dispatch_half(c, mode, ta, tb, tri, a);
+    const double bytes = (double)sizeof(TA) * m * k + (double)sizeof(TB) * k * n +
+                         2.0 * sizeof(TC) * m * n / (tri ? 2.0 : 1.0);
+    trace_end(c, kind, flops, bytes);
+}
+
+template void gemm<double, double, double>(Ctx &, Mfma, char, char, char, long long, long long,
+                                           long long, double, const double *, long long,
+                                           const double *, long long, double, double *, long long);
+template void gemm<float, float, float>(Ctx &, Mfma, char, char, char, long long, long long,
+                                        long long, double, const float *, long long,
+                                        const float *, long long, double, float *, long long);
+template void gemm<double, float, double>(Ctx &, Mfma, char, char, char, long long, long long,
+                                          long long, double, const double *, long long,
+                                          const float *, long long, double, double *, long long);
+template void gemm<float, double, double>(Ctx &, Mfma, char, char, char, long long, long long,
+                                          long long, double, const float *, long long,
+                                          const double *, long long, double, double *, long long);
+
+}  // namespace rl

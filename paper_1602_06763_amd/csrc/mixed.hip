@@ -1,0 +1,440 @@
+// Mixed-precision solves with FP64 iterative refinement.
+//
+// The factorization is the same recursion as the FP64 one, run on a
+// power-of-two scaled FP32 copy of A whose matrix-core updates use FP32, FP16
+// or BF16 operands with FP32 accumulation. FP64 is kept for the residual
+// r = b - A·x, the solution update and the correction solve, which reads the
+// low-precision factors and computes in FP64. The loop stops once the
+// normwise backward error eta = ||r||inf / (||A||inf·||x||inf + ||b||inf) of
+// every right-hand side is at most 1e-14, and falls back to the FP64
+// factorization when the low-precision one fails or refinement stalls.
+#include "common.hpp"
+
+#include <cmath>
+#include <cstring>
+
+namespace rl {
+
+enum ScratchSlot { SL_LP = 0, SL_FULL = 1, SL_VEC = 2, SL_RED = 3, SL_FB = 4, SL_PIV = 5 };
+
+__global__ void reset_info_k(DevStatus *s) {
+    if (threadIdx.x == 0) { s->info = 0; s->error = 0; s->barrier = 0u; }
+}
+
+__global__ void zero_u64_k(long long n, unsigned long long *p) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// ---- power-of-two scaling ----------------------------------------------------
+
+// t with 4^t <= x < 4^(t+1): frexp gives x = f·2^e, f in [0.5, 1)
+__device__ __forceinline__ double quarter_scale(double x) {
+    if (!(x > 0.0) || !isfinite(x)) return 1.0;
+    int e;
+    (void)frexp(x, &e);
+    const int em1 = e - 1;
+    const int t = em1 >= 0 ? em1 / 2 : -((-em1 + 1) / 2);
+    return ldexp(1.0, -t);
+}
+
+// 2^-t with 2^t <= x < 2^(t+1)
+__device__ __forceinline__ double half_scale(double x) {
+    if (!(x > 0.0) || !isfinite(x)) return 1.0;
+    int e;
+    (void)frexp(x, &e);
+    return ldexp(1.0, -(e - 1));
+}
+
+__global__ void spd_diag_scale_k(long long n, const double *A, long long lda, double *d) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = quarter_scale(A[i + i * lda]);
+}
+
+__global__ void spd_convert_k(long long n, const double *__restrict__ A, long long lda,
+                              const double *__restrict__ d, float *__restrict__ S, long long lds,
+                              int lower) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long j = blockIdx.y;
+    if (i >= n) return;
+    if (lower ? (i < j) : (i > j)) return;
+    S[i + j * lds] = (float)((d[i] * A[i + j * lda]) * d[j]);
+}
+
+// max |a_ij| over each row, 2-D tiles combined with an atomic max on the
+// (non-negative, hence order-preserving) bit pattern.
+__global__ void row_absmax_k(long long n, const double *__restrict__ A, long long lda,
+                             const double *__restrict__ scale, unsigned long long *rmax) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long j0 = (long long)blockIdx.y * 256, j1 = min(n, j0 + 256);
+    double mx = 0.0;
+    for (long long j = j0; j < j1; ++j) {
+        double v = fabs(A[i + j * lda]);
+        if (scale) v = fabs(scale[i] * A[i + j * lda]);
+        if (v > mx) mx = v;
+    }
+    atomicMax(&rmax[i], (unsigned long long)__double_as_longlong(mx));
+}
+
+// max over each column of |r_i·a_ij|, one workgroup per column
+__global__ __launch_bounds__(256) void col_absmax_k(long long n, const double *__restrict__ A, long long lda,
+                                                    const double *__restrict__ r, double *cmax) {
+    const long long j = blockIdx.x;
+    __shared__ double red[256];
+    double mx = 0.0;
+    for (long long i = threadIdx.x; i < n; i += 256) {
+        const double v = fabs(r[i] * A[i + j * lda]);
+        if (v > mx) mx = v;
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s && red[threadIdx.x + s] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cmax[j] = red[0];
+}
+
+__global__ void bits_to_half_scale_k(long long n, const unsigned long long *bits, double *s) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) s[i] = half_scale(__longlong_as_double((long long)bits[i]));
+}
+
+__global__ void to_half_scale_k(long long n, const double *mx, double *s) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) s[i] = half_scale(mx[i]);
+}
+
+__global__ void ge_convert_k(long long n, const double *__restrict__ A, long long lda,
+                             const double *__restrict__ r, const double *__restrict__ c,
+                             float *__restrict__ S, long long lds) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long j = blockIdx.y;
+    if (i >= n) return;
+    S[i + j * lds] = (float)((r[i] * A[i + j * lda]) * c[j]);
+}
+
+static inline unsigned blocks(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+void scale_spd_f32(Ctx &c, char uplo, long long n, const double *A, long long lda, double *d, float *S,
+                   long long lds) {
+    if (plan_record(c, PK_CONVERT, n, n, 0)) return;
+    trace_begin(c, PK_CONVERT);
+    hipLaunchKernelGGL(spd_diag_scale_k, dim3(blocks(n)), dim3(256), 0, c.stream, n, A, lda, d);
+    hipLaunchKernelGGL(spd_convert_k, dim3(blocks(n), (unsigned)n), dim3(256), 0, c.stream, n, A, lda, d, S,
+                       lds, (int)(uplo == 'L' || uplo == 'l'));
+    RL_CHECK(hipGetLastError());
+    trace_end(c, PK_CONVERT, 0.0, 6.0 * n * n);
+}
+
+void scale_ge_f32(Ctx &c, long long n, const double *A, long long lda, double *r, double *cs, float *S,
+                  long long lds) {
+    if (plan_record(c, PK_CONVERT, n, n, 0)) return;
+    unsigned long long *bits = (unsigned long long *)scratch(c, SL_RED, (size_t)n * 8);
+    if (!bits) return;
+    trace_begin(c, PK_CONVERT);
+    hipLaunchKernelGGL(zero_u64_k, dim3(blocks(n)), dim3(256), 0, c.stream, n, bits);
+    hipLaunchKernelGGL(row_absmax_k, dim3(blocks(n), blocks(n)), dim3(256), 0, c.stream, n, A, lda,
+                       (const double *)nullptr, bits);
+    hipLaunchKernelGGL(bits_to_half_scale_k, dim3(blocks(n)), dim3(256), 0, c.stream, n, bits, r);
+    hipLaunchKernelGGL(col_absmax_k, dim3((unsigned)n), dim3(256), 0, c.stream, n, A, lda, r,
+                       (double *)bits);
+    hipLaunchKernelGGL(to_half_scale_k, dim3(blocks(n)), dim3(256), 0, c.stream, n, (const double *)bits, cs);
+    hipLaunchKernelGGL(ge_convert_k, dim3(blocks(n), (unsigned)n), dim3(256), 0, c.stream, n, A, lda, r, cs, S,
+                       lds);
+    RL_CHECK(hipGetLastError());
+    trace_end(c, PK_CONVERT, 0.0, 14.0 * n * n);
+}
+
+// ---- FP64 residual and backward error ---------------------------------------
+
+// Full symmetric copy of a triangle-stored SPD matrix (for the FP64 residual).
+__global__ void symmetrize_k(long long n, const double *__restrict__ A, long long lda, double *__restrict__ F,
+                             int lower) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long j = blockIdx.y;
+    if (i >= n) return;
+    const bool in = lower ? (i >= j) : (i <= j);
+    F[i + j * n] = in ? A[i + j * lda] : A[j + i * lda];
+}
+
+__global__ void copy_cols_k(long long n, long long ncol, const double *S, long long lds, double *D,
+                            long long ldd) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long j = blockIdx.y;
+    if (i < n && j < ncol) D[i + j * ldd] = S[i + j * lds];
+}
+
+// ||A||inf partial row sums over 256-column chunks (deterministic two-pass)
+__global__ void row_abssum_part_k(long long n, const double *__restrict__ A, long long lda, double *part) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long j0 = (long long)blockIdx.y * 256, j1 = min(n, j0 + 256);
+    double s = 0.0;
+    for (long long j = j0; j < j1; ++j) s += fabs(A[i + j * lda]);
+    part[(long long)blockIdx.y * n + i] = s;
+}
+
+__global__ __launch_bounds__(256) void inf_norm_finish_k(long long n, long long nchunk, const double *part,
+                                                         double *out) {
+    __shared__ double red[256];
+    double mx = 0.0;
+    for (long long i = threadIdx.x; i < n; i += 256) {
+        double s = 0.0;
+        for (long long q = 0; q < nchunk; ++q) s += part[q * n + i];
+        if (s > mx || s != s) mx = s;
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s && (red[threadIdx.x + s] > red[threadIdx.x] || red[threadIdx.x + s] != red[threadIdx.x + s]))
+            red[threadIdx.x] = red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// eta_j for every column j (one workgroup per column); out[j] = eta_j
+__global__ __launch_bounds__(256) void col_eta_k(long long n, const double *R, long long ldr, const double *X,
+                                                 long long ldx, const double *B, long long ldb,
+                                                 const double *anorm, double *out) {
+    const long long j = blockIdx.x;
+    __shared__ double rr[256], xx[256], bb[256];
+    double r = 0, x = 0, b = 0;
+    for (long long i = threadIdx.x; i < n; i += 256) {
+        const double rv = fabs(R[i + j * ldr]), xv = fabs(X[i + j * ldx]), bv = fabs(B[i + j * ldb]);
+        if (rv > r || rv != rv) r = rv;
+        if (xv > x || xv != xv) x = xv;
+        if (bv > b) b = bv;
+    }
+    rr[threadIdx.x] = r; xx[threadIdx.x] = x; bb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const int t = threadIdx.x;
+            if (rr[t + s] > rr[t] || rr[t + s] != rr[t + s]) rr[t] = rr[t + s];
+            if (xx[t + s] > xx[t] || xx[t + s] != xx[t + s]) xx[t] = xx[t + s];
+            if (bb[t + s] > bb[t]) bb[t] = bb[t + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double den = (*anorm) * xx[0] + bb[0];
+        out[j] = den > 0.0 ? rr[0] / den : (rr[0] > 0.0 ? INFINITY : 0.0);
+    }
+}
+
+__global__ void max_of_k(long long n, const double *v, double *out) {
+    __shared__ double red[256];
+    double mx = 0.0;
+    for (long long i = threadIdx.x; i < n; i += 256)
+        if (v[i] > mx || v[i] != v[i]) mx = v[i];
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s && (red[threadIdx.x + s] > red[threadIdx.x] || red[threadIdx.x + s] != red[threadIdx.x + s]))
+            red[threadIdx.x] = red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// Y[i,j] = s[i] * X[i,j] (s may be null: plain copy)
+__global__ void scale_rows_k(long long n, long long ncol, const double *s, const double *X, long long ldx,
+                             double *Y, long long ldy) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long j = blockIdx.y;
+    if (i >= n) return;
+    const double v = X[i + j * ldx];
+    Y[i + j * ldy] = s ? s[i] * v : v;
+}
+
+// X[i,j] += s[i] * D[i,j]
+__global__ void axpy_rows_k(long long n, long long ncol, const double *s, const double *D, long long ldd,
+                            double *X, long long ldx) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long j = blockIdx.y;
+    if (i >= n) return;
+    X[i + j * ldx] += s[i] * D[i + j * ldd];
+}
+
+// ---- the refinement driver -----------------------------------------------------
+
+struct MixedWork {
+    float *S = nullptr;        // n×n low-precision factors
+    double *Af = nullptr;      // full FP64 matrix for the residual (SPD: symmetrized copy)
+    long long ldaf = 0;
+    double *s1 = nullptr, *s2 = nullptr;   // scalings (d, or r and c)
+    double *R = nullptr, *D = nullptr;     // residual, correction (n×nrhs)
+    double *eta = nullptr;                 // nrhs column backward errors
+    double *scal = nullptr;                // [0] ||A||inf, [1] max eta
+    double *part = nullptr;                // row-sum partials
+    int *ipiv = nullptr;
+};
+
+static double fetch_scalar(Ctx &c, const double *dptr) {
+    double h = 0.0;
+    RL_CHECK(hipMemcpyAsync(&h, dptr, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    RL_CHECK(hipStreamSynchronize(c.stream));
+    return h;
+}
+
+static int fetch_info(Ctx &c) {
+    RL_CHECK(hipMemcpyAsync(c.hstat, c.dstat, sizeof(DevStatus), hipMemcpyDeviceToHost, c.stream));
+    RL_CHECK(hipStreamSynchronize(c.stream));
+    return c.hstat->error ? -2000 - c.hstat->error : c.hstat->info;
+}
+
+static Mfma prec_mode(int prec) {
+    if (prec == 16) return Mfma::F16;
+    if (prec == 'b' || prec == 'B') return Mfma::BF16;
+    return Mfma::F32;
+}
+
+// R = B - Af·X, eta per column, returns max eta (one 8-byte read-back)
+static double residual_eta(Ctx &c, long long n, long long nrhs, MixedWork &w, const double *B, long long ldb,
+                           const double *X, long long ldx) {
+    trace_begin(c, PK_RESID);
+    hipLaunchKernelGGL(copy_cols_k, dim3(blocks(n), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs, B, ldb,
+                       w.R, n);
+    trace_end(c, PK_RESID, 0.0, 16.0 * n * nrhs);
+    gemm<double, double, double>(c, Mfma::F64, 'N', 'N', 0, n, nrhs, n, -1.0, w.Af, w.ldaf, X, ldx, 1.0, w.R, n);
+    hipLaunchKernelGGL(col_eta_k, dim3((unsigned)nrhs), dim3(256), 0, c.stream, n, w.R, n, X, ldx, B, ldb,
+                       w.scal, w.eta);
+    hipLaunchKernelGGL(max_of_k, dim3(1), dim3(256), 0, c.stream, nrhs, w.eta, w.scal + 1);
+    RL_CHECK(hipGetLastError());
+    return fetch_scalar(c, w.scal + 1);
+}
+
+static void inf_norm(Ctx &c, long long n, const double *A, long long lda, MixedWork &w) {
+    const long long nchunk = (n + 255) / 256;
+    hipLaunchKernelGGL(row_abssum_part_k, dim3(blocks(n), (unsigned)nchunk), dim3(256), 0, c.stream, n, A, lda,
+                       w.part);
+    hipLaunchKernelGGL(inf_norm_finish_k, dim3(1), dim3(256), 0, c.stream, n, nchunk, w.part, w.scal);
+    RL_CHECK(hipGetLastError());
+}
+
+// D = A_lp⁻¹·R through the scaled low-precision factors, in FP64 arithmetic
+static void correction(Ctx &c, bool spd, char uplo, long long n, long long nrhs, MixedWork &w) {
+    const dim3 g(blocks(n), (unsigned)nrhs);
+    // D = s1 ∘ R   (SPD: D·r;  general: R·r)
+    hipLaunchKernelGGL(scale_rows_k, g, dim3(256), 0, c.stream, n, nrhs, (const double *)w.s1, w.R, n, w.D, n);
+    if (spd) {
+        if (uplo == 'L') {
+            trsm<float, double>(c, Mfma::F64, 'L', 'L', 'N', 'N', n, nrhs, w.S, n, w.D, n);
+            trsm<float, double>(c, Mfma::F64, 'L', 'L', 'T', 'N', n, nrhs, w.S, n, w.D, n);
+        } else {
+            trsm<float, double>(c, Mfma::F64, 'L', 'U', 'T', 'N', n, nrhs, w.S, n, w.D, n);
+            trsm<float, double>(c, Mfma::F64, 'L', 'U', 'N', 'N', n, nrhs, w.S, n, w.D, n);
+        }
+    } else {
+        laswp_rows<double>(c, nrhs, w.D, n, w.ipiv, 0, n, false);
+        trsm<float, double>(c, Mfma::F64, 'L', 'L', 'N', 'U', n, nrhs, w.S, n, w.D, n);
+        trsm<float, double>(c, Mfma::F64, 'L', 'U', 'N', 'N', n, nrhs, w.S, n, w.D, n);
+    }
+}
+
+// Returns info; *iter and *berr as documented in relapack.h.
+int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const double *A, long long lda,
+                int *ipiv_out, const double *B, long long ldb, double *X, long long ldx, int prec, int *iter,
+                double *berr) {
+    const double tol = 1e-14;
+    const int max_sweeps = 30;
+    MixedWork w;
+    w.S = (float *)scratch(c, SL_LP, (size_t)n * n * sizeof(float));
+    w.ldaf = spd ? n : lda;
+    if (spd) w.Af = (double *)scratch(c, SL_FULL, (size_t)n * n * sizeof(double));
+    else w.Af = const_cast<double *>(A);
+    const long long nchunk = (n + 255) / 256;
+    const size_t vec = (size_t)(2 * n + 2 * n * nrhs + nrhs + 2 + nchunk * n);
+    double *v = (double *)scratch(c, SL_VEC, vec * sizeof(double));
+    w.ipiv = spd ? nullptr : (ipiv_out ? ipiv_out : (int *)scratch(c, SL_PIV, (size_t)n * sizeof(int)));
+    if (!w.S || !w.Af || !v) return -1000 - (int)hipErrorOutOfMemory;
+    w.s1 = v; w.s2 = v + n; w.R = v + 2 * n; w.D = w.R + n * nrhs; w.eta = w.D + n * nrhs;
+    w.scal = w.eta + nrhs; w.part = w.scal + 2;
+
+    // scaling + conversion, FP64 copy for the residual, ||A||inf
+    if (spd) {
+        scale_spd_f32(c, uplo, n, A, lda, w.s1, w.S, n);
+        hipLaunchKernelGGL(symmetrize_k, dim3(blocks(n), (unsigned)n), dim3(256), 0, c.stream, n, A, lda, w.Af,
+                           (int)(uplo == 'L'));
+    } else {
+        scale_ge_f32(c, n, A, lda, w.s1, w.s2, w.S, n);
+    }
+    inf_norm(c, n, w.Af, w.ldaf, w);
+
+    // low-precision factorization (status reset: its info is its own)
+    const Mfma mode = prec_mode(prec);
+    c.abort_on_info = spd;
+    if (spd) potrf_rec<float>(c, mode, uplo, n, w.S, n, 0);
+    else getrf_top<float>(c, mode, n, n, w.S, n, w.ipiv);
+    c.abort_on_info = false;
+    const int lp_info = fetch_info(c);
+    int status = 0;  // 0 running, 1 converged, -3 lp failed, -31 stalled
+    double eta = INFINITY;
+    int sweeps = 0;
+    if (lp_info != 0) status = -3;
+
+    if (status == 0) {
+        // x0 = A_lp⁻¹·b (as a correction of x = 0, residual r = b)
+        hipLaunchKernelGGL(copy_cols_k, dim3(blocks(n), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs, B, ldb,
+                           w.R, n);
+        correction(c, spd, uplo, n, nrhs, w);
+        const double *cs = spd ? w.s1 : w.s2;
+        hipLaunchKernelGGL(scale_rows_k, dim3(blocks(n), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs, cs,
+                           w.D, n, X, ldx);
+        double prev = INFINITY;
+        for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
+            eta = residual_eta(c, n, nrhs, w, B, ldb, X, ldx);
+            if (eta <= tol) { status = 1; break; }
+            if (!(eta == eta) || (sweeps > 3 && eta > 0.5 * prev)) { status = -31; break; }
+            prev = eta;
+            correction(c, spd, uplo, n, nrhs, w);
+            hipLaunchKernelGGL(axpy_rows_k, dim3(blocks(n), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs, cs,
+                               w.D, n, X, ldx);
+        }
+        if (status == 0) status = -31;
+    }
+
+    if (status == 1) {
+        *iter = sweeps;
+        *berr = eta;
+        return 0;
+    }
+    // FP64 fallback on a copy of A (A itself is never modified)
+    double *F = (double *)scratch(c, SL_FB, (size_t)n * n * sizeof(double));
+    if (!F) return -1000 - (int)hipErrorOutOfMemory;
+    hipLaunchKernelGGL(copy_cols_k, dim3(blocks(n), (unsigned)n), dim3(256), 0, c.stream, n, n, A, lda, F, n);
+    hipLaunchKernelGGL(copy_cols_k, dim3(blocks(n), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs, B, ldb, X,
+                       ldx);
+    hipLaunchKernelGGL(reset_info_k, dim3(1), dim3(64), 0, c.stream, c.dstat);
+    c.barrier_base = 0;  // the arrival counter was reset with the status block
+    int info = 0;
+    if (spd) {
+        c.abort_on_info = true;
+        potrf_rec<double>(c, Mfma::F64, uplo, n, F, n, 0);
+        c.abort_on_info = false;
+        info = fetch_info(c);
+        if (info == 0) {
+            if (uplo == 'L') {
+                trsm<double, double>(c, Mfma::F64, 'L', 'L', 'N', 'N', n, nrhs, F, n, X, ldx);
+                trsm<double, double>(c, Mfma::F64, 'L', 'L', 'T', 'N', n, nrhs, F, n, X, ldx);
+            } else {
+                trsm<double, double>(c, Mfma::F64, 'L', 'U', 'T', 'N', n, nrhs, F, n, X, ldx);
+                trsm<double, double>(c, Mfma::F64, 'L', 'U', 'N', 'N', n, nrhs, F, n, X, ldx);
+            }
+        }
+    } else {
+        getrf_top<double>(c, Mfma::F64, n, n, F, n, w.ipiv);
+        info = fetch_info(c);
+        laswp_rows<double>(c, nrhs, X, ldx, w.ipiv, 0, n, false);
+        trsm<double, double>(c, Mfma::F64, 'L', 'L', 'N', 'U', n, nrhs, F, n, X, ldx);
+        trsm<double, double>(c, Mfma::F64, 'L', 'U', 'N', 'N', n, nrhs, F, n, X, ldx);
+    }
+    *iter = status;
+    *berr = (spd && info != 0) ? INFINITY : residual_eta(c, n, nrhs, w, B, ldb, X, ldx);
+    return info;
+}
+
+}  // namespace rl

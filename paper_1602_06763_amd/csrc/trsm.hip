@@ -1,0 +1,363 @@
+// Triangular solves with many right-hand sides (BLAS-3 xtrsm), recursive.
+//
+// The recursion splits the triangle in two (the paper's block-size-n/2 rule,
+// Sec. 3) so that every off-diagonal flop is a matrix-core GEMM; the leaf is a
+// substitution kernel. Substitution (never an explicitly inverted diagonal
+// block) keeps every step an exact operation on exactly representable data,
+// which the integer test matrices rely on.
+//
+// Leaf: solve N·x = b for many vectors b, N a t×t triangle (t <= 64) held in
+// LDS. Each lane owns one right-hand-side vector and keeps it in registers.
+// Element (i, j) of N is T[i*ti + j*tj]; element e of vector r is
+// B[e*se + r*sr]. Left-side solves use se = 1 (columns of B), right-side
+// solves use sr = 1 (rows of B) with N = op(T)ᵀ.
+#include "common.hpp"
+
+#include <type_traits>
+
+namespace rl {
+
+// Column-oriented substitution: once x_j is known every later x_i receives
+// its -N(i,j)·x_j at once, so a lane's 2016 multiply-adds are independent
+// within each column and pipeline instead of forming one long chain. N is
+// held transposed in LDS (NT[j][i] = N(i,j)) so a column is contiguous and the
+// broadcast reads pair up. FULL: t == 64 without per-element guards (kept for
+// reference; it spills, so the launcher always takes the guarded form).
+template <typename TT, typename TB, typename TW, bool FULL, bool LOWER>
+__global__ __launch_bounds__(256) void trsm_leaf_k(int unit, int t, const TT *__restrict__ T,
+                                                   long long ti, long long tj, long long nvec,
+                                                   TB *__restrict__ B, long long se, long long sr,
+                                                   const int *abort) {
+    if (abort && *abort) return;
+    __shared__ __attribute__((aligned(16))) TW NT[64][64 + 2];
+    const int tid = threadIdx.x;
+    // 16 unconditional loads per thread (t*t <= 4096), clamped to the triangle's corner
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int idx = tid + 256 * u;
+        const int i = idx % 64, j = idx / 64;
+        const bool in = i < t && j < t && (LOWER ? (j <= i) : (j >= i));
+        const TW v = (TW)T[(in ? i : 0) * ti + (in ? j : 0) * tj];
+        NT[j][i] = in ? v : TW(0);
+    }
+    __syncthreads();
+    const long long r = (long long)blockIdx.x * 256 + tid;
+    if (r >= nvec) return;
+    TB *b = B + r * sr;
+    TW x[64];
+    // 8 loads at a time: 64 precomputed 64-bit addresses would not fit beside x
+#pragma unroll
+    for (int e = 0; e < 64; ++e) {
+        const TW v = (TW)b[(e < t ? e : t - 1) * se];   // clamped, unconditional
+        x[e] = (FULL || e < t) ? v : TW(0);
+        if ((e & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+
+    if (LOWER) {
+#pragma unroll
+        for (int j = 0; j < 64; ++j) {
+            if (FULL || j < t) {
+                const TW xj = unit ? x[j] : x[j] / NT[j][j];
+                x[j] = xj;
+#pragma unroll
+                for (int i = j + 1; i < 64; ++i) {
+                    if (FULL || i < t) x[i] -= NT[j][i] * xj;
+                    // bound how many LDS reads are in flight (x already holds 64 registers)
+                    if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+#pragma unroll
+        for (int j = 63; j >= 0; --j) {
+            if (FULL || j < t) {
+                const TW xj = unit ? x[j] : x[j] / NT[j][j];
+                x[j] = xj;
+#pragma unroll
+                for (int i = 0; i < j; ++i) {
+                    x[i] -= NT[j][i] * xj;
+                    if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    // an opaque copy of the row pointer: the store addresses are recomputed
+    // instead of keeping all 64 load addresses live across the solve
+    TB *bs = b;
+    asm volatile("" : "+v"(bs));
+#pragma unroll
+    for (int e = 0; e < 64; ++e) {
+        if (FULL || e < t) bs[e * se] = (TB)x[e];
+        if ((e & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <typename TT, typename TB>
+void trsm_leaf(Ctx &c, bool lower_eff, bool unit, int t, const TT *T, long long ti, long long tj,
+               long long nvec, TB *B, long long se, long long sr) {
+    if (plan_record(c, PK_TRSM_LEAF, t, nvec, t)) return;
+    if (t <= 0 || nvec <= 0) return;
+    const int grid = (int)((nvec + 255) / 256);
+    const int *abort = c.abort_on_info ? &c.dstat->info : nullptr;
+    trace_begin(c, PK_TRSM_LEAF);
+    typedef typename std::conditional<(sizeof(TB) == 8 || sizeof(TT) == 8), double, float>::type TW;
+#define RL_LEAF(F, L)                                                                        \
+    hipLaunchKernelGGL((trsm_leaf_k<TT, TB, TW, F, L>), dim3(grid), dim3(256), 0, c.stream,    \
+                       (int)unit, t, T, ti, tj, nvec, B, se, sr, abort)
+    // the guarded form: the unguarded straight-line variant exhausts the VGPRs
+    if (lower_eff) RL_LEAF(false, true); else RL_LEAF(false, false);
+#undef RL_LEAF
+    RL_CHECK(hipGetLastError());
+    trace_end(c, PK_TRSM_LEAF, (double)t * t * nvec, 8.0 * (t * t + 2.0 * t * nvec));
+}
+
+
+// ---------------------------------------------------------------------------
+// Blocked triangular solve for a few right-hand sides (nrhs <= 8 per launch):
+// one launch for the whole triangle. Workgroups take 64-row blocks in the
+// order they start (a ticket counter), so a workgroup only ever waits on
+// blocks owned by workgroups that started before it. Each of its 4 waves
+// accumulates op(T)(block, j)·x_j over every fourth earlier block j as soon as
+// that block's solution is published; wave 0 then solves the 64×64 diagonal
+// block with lanes over rows (readlane broadcasts x_k) and publishes x_b.
+// Published solutions go through a separate buffer written and read with
+// device-coherent atomic accesses, and the ready flag is set only after those
+// stores have completed. The triangle is read once: the solve is bound by HBM
+// bandwidth and by the chain of n/64 diagonal solves.
+// ---------------------------------------------------------------------------
+struct TrsvArgs {
+    long long n;
+    int nrhs, nb;
+    long long ldt, ldb;
+    int trans, lower_eff, unit, epoch;
+    unsigned long long *ticket;
+    unsigned long long ticket_base;
+    int *ready;
+    double *xbuf;   // [n][8]
+    DevStatus *st;
+};
+
+__device__ __forceinline__ double rl_readlane(double x, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
+template <typename TT, typename TB, int NR>
+__global__ __launch_bounds__(256) void trsv_k(const TT *__restrict__ T, TB *__restrict__ B, TrsvArgs a) {
+    __shared__ double xs[4][64][NR];
+    __shared__ double red[4][64][NR];
+    __shared__ double Dsh[64][65];
+    __shared__ int bsh;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) bsh = (int)(atomicAdd(a.ticket, 1ull) - a.ticket_base);
+    __syncthreads();
+    const int b = bsh, nb = a.nb;
+    // the diagonal block, loaded by the whole workgroup before any wait
+    {
+        const bool fwd0 = a.lower_eff != 0;
+        const long long rb = (long long)(fwd0 ? b : nb - 1 - b) * 64;
+        const int nr0 = (int)min(64LL, a.n - rb);
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, ii = idx % 64, kk = idx / 64;
+            const bool in = ii < nr0 && kk < nr0;
+            const long long r = rb + (in ? ii : 0), cc = rb + (in ? kk : 0);
+            v[u] = (double)(a.trans ? T[cc + r * a.ldt] : T[r + cc * a.ldt]);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, ii = idx % 64, kk = idx / 64;
+            const bool in = ii < nr0 && kk < nr0;
+            Dsh[ii][kk] = in ? v[u] : (ii == kk ? 1.0 : 0.0);
+        }
+    }
+    const bool fwd = a.lower_eff != 0;
+    const long long n = a.n;
+    const int pb = fwd ? b : nb - 1 - b;
+    const long long r0 = (long long)pb * 64;
+    const int nrow = (int)min(64LL, n - r0);
+    const int nq = a.nrhs;
+    const long long ri = r0 + lane;
+    // element (r, c) of op(T)
+    auto M = [&](long long r, long long c) -> double {
+        return (double)(a.trans ? T[c + r * a.ldt] : T[r + c * a.ldt]);
+    };
+
+    double acc[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] = 0.0;
+    for (int jj = wave; jj < b; jj += 4) {
+        const int pj = fwd ? jj : nb - 1 - jj;
+        const long long c0 = (long long)pj * 64;
+        const int ncol = (int)min(64LL, n - c0);
+        if (lane == 0) {
+            unsigned int spins = 0;
+            while (__hip_atomic_load(&a.ready[jj], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != a.epoch) {
+                if (++spins > (1u << 24)) { atomicExch(&a.st->error, 2); break; }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane < ncol) {
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                xs[wave][lane][q] = q < nq ? __hip_atomic_load(&a.xbuf[(c0 + lane) * 8 + q], __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT)
+                                           : 0.0;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane < nrow) {
+            // 16 matrix loads in flight at a time
+            for (int k0 = 0; k0 < ncol; k0 += 16) {
+                double mk[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const double v = M(ri, c0 + min(k0 + u, ncol - 1));   // clamped, unconditional
+                    mk[u] = (k0 + u < ncol) ? v : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) acc[q] -= mk[u] * xs[wave][min(k0 + u, 63)][q];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) red[wave][lane][q] = acc[q];
+    __syncthreads();
+    if (wave == 0) {
+        double r[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            double v = (lane < nrow && q < nq) ? (double)B[ri + q * a.ldb] : 0.0;
+            r[q] = v + red[0][lane][q] + red[1][lane][q] + red[2][lane][q] + red[3][lane][q];
+        }
+        for (int s = 0; s < nrow; ++s) {
+            const int k = fwd ? s : nrow - 1 - s;   // uniform
+            const double dkk = Dsh[lane][k];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                const double xk = rl_readlane(a.unit ? r[q] : r[q] / dkk, k);
+                if (lane == k) r[q] = xk;
+                else if (fwd ? lane > k : lane < k) r[q] -= dkk * xk;
+            }
+        }
+        if (lane < nrow) {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                if (q < nq) {
+                    B[ri + q * a.ldb] = (TB)r[q];
+                    __hip_atomic_store(&a.xbuf[ri * 8 + q], r[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);   // published values have completed
+    }
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(&a.ready[b], a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename TT, typename TB>
+static void trsv(Ctx &c, bool lower_eff, bool trans, bool unit, long long m, long long nrhs, const TT *T,
+                 long long ldt, TB *B, long long ldb) {
+    const int nb = (int)((m + 63) / 64);
+    TrsvWork wk = trsv_work(c, m, nb, (int)((nrhs + 7) / 8));
+    if (!wk.xbuf) return;
+    trace_begin(c, PK_TRSM_LEAF);
+    for (long long q0 = 0; q0 < nrhs; q0 += 8) {
+        TrsvArgs a{};
+        a.n = m; a.nrhs = (int)min(8LL, nrhs - q0); a.nb = nb;
+        a.ldt = ldt; a.ldb = ldb;
+        a.trans = trans; a.lower_eff = lower_eff; a.unit = unit;
+        a.epoch = wk.epoch + (int)(q0 / 8);
+        a.ticket = wk.ticket;
+        a.ticket_base = wk.ticket_base + (unsigned long long)nb * (unsigned long long)(q0 / 8);
+        a.ready = wk.ready;
+        a.xbuf = wk.xbuf;
+        a.st = c.dstat;
+        if (a.nrhs == 1)
+            hipLaunchKernelGGL((trsv_k<TT, TB, 1>), dim3(nb), dim3(256), 0, c.stream, T, B + q0 * ldb, a);
+        else
+            hipLaunchKernelGGL((trsv_k<TT, TB, 8>), dim3(nb), dim3(256), 0, c.stream, T, B + q0 * ldb, a);
+        RL_CHECK(hipGetLastError());
+    }
+    trace_end(c, PK_TRSM_LEAF, (double)m * m * nrhs, (double)sizeof(TT) * m * m / 2.0 + 16.0 * m * nrhs);
+}
+
+static inline bool is(char a, char b) { return a == b || a == (b + ('a' - 'A')); }
+
+// Pointer to the block op(T)[r0:, c0:] and the op to use for it.
+template <typename TT>
+static inline const TT *opblock(const TT *T, long long ldt, bool trans, long long r0, long long c0) {
+    return trans ? T + c0 + r0 * ldt : T + r0 + c0 * ldt;
+}
+
+template <typename TT, typename TB>
+void trsm(Ctx &c, Mfma mode, char side, char uplo, char trans, char diag, long long m, long long n,
+          const TT *T, long long ldt, TB *B, long long ldb) {
+    if (m <= 0 || n <= 0) return;
+    const bool tr = is(trans, 'T') || is(trans, 'C');
+    const bool lowerM = is(uplo, 'L') != tr;  // op(T) is lower triangular
+    const bool unit = is(diag, 'U');
+    const char opc = tr ? 'T' : 'N';
+    const int leaf = c.plan && c.plan_leaf > 0 ? c.plan_leaf : kTrsmLeaf;
+    if (is(side, 'L')) {
+        // op(T)·X = B, X m×n, triangle m×m
+        if (!c.plan && n <= kTrsvMaxRhs && m > leaf) {
+            trsv<TT, TB>(c, lowerM, tr, unit, m, n, T, ldt, B, ldb);
+            return;
+        }
+        if (m <= leaf) {
+            trsm_leaf<TT, TB>(c, lowerM, unit, (int)m, T, tr ? ldt : 1, tr ? 1 : ldt, n, B, 1, ldb);
+            return;
+        }
+        const long long m1 = split_size(m), m2 = m - m1;
+        const TT *T22 = T + m1 + m1 * ldt;
+        if (lowerM) {
+            trsm<TT, TB>(c, mode, side, uplo, trans, diag, m1, n, T, ldt, B, ldb);
+            gemm<TT, TB, TB>(c, mode, opc, 'N', 0, m2, n, m1, -1.0, opblock(T, ldt, tr, m1, 0), ldt, B,
+                             ldb, 1.0, B + m1, ldb);
+            trsm<TT, TB>(c, mode, side, uplo, trans, diag, m2, n, T22, ldt, B + m1, ldb);
+        } else {
+            trsm<TT, TB>(c, mode, side, uplo, trans, diag, m2, n, T22, ldt, B + m1, ldb);
+            gemm<TT, TB, TB>(c, mode, opc, 'N', 0, m1, n, m2, -1.0, opblock(T, ldt, tr, 0, m1), ldt,
+                             B + m1, ldb, 1.0, B, ldb);
+            trsm<TT, TB>(c, mode, side, uplo, trans, diag, m1, n, T, ldt, B, ldb);
+        }
+    } else {
+        // X·op(T) = B, X m×n, triangle n×n. Row r of X solves op(T)ᵀ·xᵀ = bᵀ.
+        if (n <= leaf) {
+            // N = op(T)ᵀ: N(i,j) = op(T)(j,i) = tr ? T(i,j) : T(j,i)
+            trsm_leaf<TT, TB>(c, !lowerM, unit, (int)n, T, tr ? 1 : ldt, tr ? ldt : 1, m, B, ldb, 1);
+            return;
+        }
+        const long long n1 = split_size(n), n2 = n - n1;
+        const TT *T22 = T + n1 + n1 * ldt;
+        if (!lowerM) {
+            // op(T) upper: X1 first, then B2 -= X1·op(T)12
+            trsm<TT, TB>(c, mode, side, uplo, trans, diag, m, n1, T, ldt, B, ldb);
+            gemm<TB, TT, TB>(c, mode, 'N', opc, 0, m, n2, n1, -1.0, B, ldb, opblock(T, ldt, tr, 0, n1),
+                             ldt, 1.0, B + n1 * ldb, ldb);
+            trsm<TT, TB>(c, mode, side, uplo, trans, diag, m, n2, T22, ldt, B + n1 * ldb, ldb);
+        } else {
+            // op(T) lower: X2 first, then B1 -= X2·op(T)21
+            trsm<TT, TB>(c, mode, side, uplo, trans, diag, m, n2, T22, ldt, B + n1 * ldb, ldb);
+            gemm<TB, TT, TB>(c, mode, 'N', opc, 0, m, n1, n2, -1.0, B + n1 * ldb, ldb,
+                             opblock(T, ldt, tr, n1, 0), ldt, 1.0, B, ldb);
+            trsm<TT, TB>(c, mode, side, uplo, trans, diag, m, n1, T, ldt, B, ldb);
+        }
+    }
+}
+
+template void trsm<double, double>(Ctx &, Mfma, char, char, char, char, long long, long long,
+                                   const double *, long long, double *, long long);
+template void trsm<float, float>(Ctx &, Mfma, char, char, char, char, long long, long long,
+                                 const float *, long long, float *, long long);
+template void trsm<float, double>(Ctx &, Mfma, char, char, char, char, long long, long long,
+                                  const float *, long long, double *, long long);
+
+}  // namespace rl

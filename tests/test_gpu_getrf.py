@@ -1,0 +1,141 @@
+"""GPU parity of the recursive LU with partial pivoting (relapack_dgetrf /
+dgetrs) against the CPU oracle, through the C ABI. Bars: ipiv bit-exact; exact
+dyadic constructions bit-exact in L and U; ||P·A - L·U||_F <= 10·n·u·||A||_F;
+|l_ij| <= 1; L/U within 1e-12 of the oracle on well-conditioned inputs."""
+import numpy as np
+import pytest
+
+import gen
+import paper_1602_06763_amd as rl
+from gpu_util import U64, ipiv_dev, rel_fro, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(a, ld=None):
+    m, n = a.shape
+    t = to_dev(a, ld)
+    piv = ipiv_dev(min(m, n))
+    info = rl.getrf(t, piv)
+    return to_host(t), piv.cpu().numpy()[: min(m, n)], info
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (2, 2), (31, 31), (32, 32), (33, 33), (64, 64), (100, 100),
+                                 (257, 257), (600, 600), (1000, 1000), (2048, 2048), (300, 120),
+                                 (120, 300), (1500, 40), (40, 1500), (2000, 1500), (513, 700)])
+def test_random_uniform(orc, m, n):
+    a = gen.general_uniform(m, n, seed=m * 7 + n)
+    f, piv, info = _run(a, ld=m + (3 if m % 3 == 0 else 0))
+    ref, rpiv, rinfo = orc.getrf(a)
+    assert info == rinfo == 0
+    assert np.array_equal(piv, rpiv)
+    L, U = orc.unpack_lu(f)
+    assert np.abs(L).max() <= 1.0
+    res = np.linalg.norm(orc.apply_ipiv(a, piv) - L @ U) / np.linalg.norm(a)
+    assert res <= 10 * max(m, n) * U64
+    # reported, and gated loosely: uniform matrices are not well conditioned
+    assert rel_fro(f, ref) <= 1e-9
+
+
+@pytest.mark.parametrize("n", [64, 500, 1200])
+def test_well_conditioned_factors(orc, n):
+    a, _, _ = gen.conditioned(n, 1e2, "general", seed=n)
+    f, piv, info = _run(a)
+    ref, rpiv, _ = orc.getrf(a)
+    assert info == 0 and np.array_equal(piv, rpiv)
+    L, U = orc.unpack_lu(f)
+    Lr, Ur = orc.unpack_lu(ref)
+    assert rel_fro(L, Lr) <= 1e-12 and rel_fro(U, Ur) <= 1e-12
+
+
+@pytest.mark.parametrize("m,n", [(7, 7), (64, 64), (300, 300), (1000, 1000), (3000, 3000), (2000, 700), (700, 2000)])
+def test_exact_dyadic(m, n):
+    a, perm, lo, up = gen.exact_lu(m, n, seed=m + 3 * n)
+    f, piv, info = _run(a)
+    k = min(m, n)
+    ipiv_ref, rows = gen.exact_lu_pivots(perm, k)
+    assert info == 0
+    assert np.array_equal(piv, ipiv_ref)
+    L = np.tril(f[:, :k], -1) + np.eye(m, k)
+    U = np.triu(f[:k, :])
+    assert np.array_equal(L, lo[rows]) and np.array_equal(U, up)
+
+
+@pytest.mark.parametrize("n", [60, 1000])
+def test_wilkinson_ties(n):
+    f, piv, info = _run(gen.wilkinson(n))
+    assert info == 0
+    assert np.array_equal(piv, np.arange(1, n + 1))
+    assert np.array_equal(f[:, n - 1], 2.0 ** np.arange(n))
+
+
+def test_diag_dominant_no_interchange():
+    n = 1500
+    f, piv, info = _run(gen.diag_dominant(n, seed=2))
+    assert info == 0 and np.array_equal(piv, np.arange(1, n + 1))
+
+
+def test_zero_pivot_completes(orc):
+    n = 200
+    a = gen.general_uniform(n, n, seed=9)
+    a[:, 40] = 0.0    # every Schur complement of this column is an exact zero: info = 41
+    a[:, 150] = 0.0   # a later exact zero pivot: no interchange, info keeps the first
+    f, piv, info = _run(a)
+    ref, rpiv, rinfo = orc.getrf(a)
+    assert info == rinfo == 41
+    assert np.array_equal(piv, rpiv)
+    L, U = orc.unpack_lu(f)
+    assert U[40, 40] == 0.0 and U[150, 150] == 0.0
+    assert piv[40] == 41 and piv[150] == 151
+    assert np.linalg.norm(orc.apply_ipiv(a, piv) - L @ U) <= 10 * n * U64 * np.linalg.norm(a)
+
+
+def test_permutation_matrix():
+    n = 257
+    pm = np.asfortranarray(np.eye(n)[gen.rng(3).permutation(n)])
+    f, piv, info = _run(pm)
+    assert info == 0
+    assert np.array_equal(f, np.eye(n))
+
+
+@pytest.mark.parametrize("trans", ["N", "T"])
+@pytest.mark.parametrize("nrhs", [1, 5, 64])
+def test_getrs(orc, trans, nrhs):
+    n = 900
+    a, perm, lo, up = gen.exact_lu(n, n, seed=11)
+    x = gen.rng(1).integers(-5, 6, size=(n, nrhs)).astype(np.float64)
+    b = (a if trans == "N" else a.T) @ x
+    t = to_dev(a)
+    piv = ipiv_dev(n)
+    assert rl.getrf(t, piv) == 0
+    bt = to_dev(b)
+    assert rl.getrs(t, piv, bt, trans) == 0
+    assert np.array_equal(to_host(bt), x)
+    g = gen.general_uniform(n, n, seed=12)
+    b2 = gen.general_uniform(n, nrhs, seed=13)
+    t = to_dev(g)
+    rl.getrf(t, piv)
+    bt = to_dev(b2)
+    rl.getrs(t, piv, bt, trans)
+    assert orc.backward_error(g if trans == "N" else g.T, to_host(bt), b2)[0] <= 10 * n * U64
+
+
+@pytest.mark.parametrize("m,n", [(20000, 64), (40000, 40)])
+def test_tall_panels_many_workgroups(orc, m, n):
+    """Tall panels spread over 40 and 79 cooperating workgroups (records staged in
+    LDS, and read straight from memory beyond 64 workgroups)."""
+    a = gen.general_uniform(m, n, seed=m + n)
+    f, piv, info = _run(a)
+    ref, rpiv, rinfo = orc.getrf(a)
+    assert info == rinfo == 0
+    assert np.array_equal(piv, rpiv)
+    assert rel_fro(f, ref) <= 1e-12
+
+
+def test_tall_exact_dyadic():
+    m, n = 30000, 96
+    a, perm, lo, up = gen.exact_lu(m, n, seed=5)
+    f, piv, info = _run(a)
+    ipiv_ref, rows = gen.exact_lu_pivots(perm, n)
+    assert info == 0 and np.array_equal(piv, ipiv_ref)
+    assert np.array_equal(np.tril(f, -1) + np.eye(m, n), lo[rows]) and np.array_equal(np.triu(f[:n]), up)
