@@ -19,8 +19,8 @@ struct DevState {
     bool init = false;
     DevStatus *dstat = nullptr;
     DevStatus *hstat = nullptr;
-    double *panel_rec = nullptr;
-    size_t panel_rec_elems = 0;
+    unsigned long long *panel_rec = nullptr;
+    unsigned int panel_epoch = 0;   // next free epoch of the panel records
     int *rowsrc = nullptr;
     size_t rowsrc_elems = 0;
     void *slot[kScratchSlots] = {};
@@ -56,6 +56,11 @@ __global__ void fill_int_k(int *p, long long n, int v) {
     if (i < n) p[i] = v;
 }
 
+__global__ void fill_u64_k(unsigned long long *p, long long n, unsigned long long v) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void zero_u64_one_k(unsigned long long *p) {
     if (threadIdx.x == 0) *p = 0ull;
 }
@@ -84,15 +89,11 @@ void ensure_device(Ctx &c) {
         if (hipGetDeviceProperties(&p, dev) == hipSuccess) d.num_cu = p.multiProcessorCount;
         RL_CHECK(hipMalloc(&d.dstat, sizeof(DevStatus)));
         RL_CHECK(hipHostMalloc(&d.hstat, sizeof(DevStatus), hipHostMallocDefault));
-        d.panel_rec_elems = (size_t)2 * (kPanelMaxWG + 1) * (kLuLeaf + 4);
-        RL_CHECK(hipMalloc(&d.panel_rec, d.panel_rec_elems * sizeof(double)));
         d.init = true;
     }
     c.device = dev;
     c.dstat = d.dstat;
     c.hstat = d.hstat;
-    c.panel_rec = d.panel_rec;
-    c.panel_rec_elems = d.panel_rec_elems;
     c.rowsrc = d.rowsrc;
     c.rowsrc_elems = d.rowsrc_elems;
     c.num_cu = d.num_cu;
@@ -125,6 +126,31 @@ void *scratch(Ctx &c, int slot, size_t bytes) {
         d.slot_bytes[slot] = bytes;
     }
     return d.slot[slot];
+}
+
+unsigned long long *panel_records(Ctx &c, unsigned int *epoch) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState &d = g_dev[c.device];
+    const long long words = (long long)kLuLeaf * kRecSlots * kRecWords;
+    if (!d.panel_rec) {
+        if (hipMalloc(&d.panel_rec, (size_t)words * sizeof(unsigned long long)) != hipSuccess) {
+            d.panel_rec = nullptr;
+            launch_error(hipErrorOutOfMemory);
+            return nullptr;
+        }
+        d.panel_epoch = 0;
+    }
+    // epochs below 2·kLuLeaf are never handed out, so zeroed words never match;
+    // on wrap-around the records are cleared again (stream-ordered before the panel)
+    if (d.panel_epoch < 2u * kLuLeaf || d.panel_epoch > 0xFFFFFFFFu - 2u * kLuLeaf) {
+        hipLaunchKernelGGL(fill_u64_k, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, c.stream, d.panel_rec,
+                           words, 0ull);
+        RL_CHECK(hipGetLastError());
+        d.panel_epoch = 2u * kLuLeaf;
+    }
+    *epoch = d.panel_epoch;
+    d.panel_epoch += kLuLeaf;
+    return d.panel_rec;
 }
 
 TrsvWork trsv_work(Ctx &c, long long m, int nb, int launches) {
@@ -196,7 +222,6 @@ static bool call_begin(Ctx &c, bool abort_on_info) {
     ensure_device(c);
     if (t_err) return false;
     c.abort_on_info = abort_on_info;
-    c.barrier_base = 0;
     c.level = 0;
     hipLaunchKernelGGL(reset_status_k, dim3(1), dim3(64), 0, c.stream, c.dstat);
     RL_CHECK(hipGetLastError());
@@ -241,7 +266,7 @@ void relapack_finalize(void) {
         (void)hipDeviceSynchronize();
         (void)hipFree(d.dstat);
         (void)hipHostFree(d.hstat);
-        (void)hipFree(d.panel_rec);
+        if (d.panel_rec) (void)hipFree(d.panel_rec);
         if (d.rowsrc) (void)hipFree(d.rowsrc);
         if (d.trsv_x) (void)hipFree(d.trsv_x);
         if (d.trsv_ready) (void)hipFree(d.trsv_ready);

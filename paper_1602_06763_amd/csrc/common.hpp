@@ -27,6 +27,9 @@ constexpr int kCholLeaf = 64;       // potf2 leaf: n <= kCholLeaf
 constexpr int kTrsmLeaf = 64;       // triangular solve leaf: triangle <= kTrsmLeaf
 constexpr int kLuLeaf = 32;         // getf2 panel width
 constexpr int kPanelMaxWG = 256;    // cooperative panel: at most one workgroup per CU
+constexpr int kPanelRows = 512;     // panel rows per workgroup (two per thread)
+constexpr int kRecWords = 72;       // 64-bit words per panel exchange record
+constexpr int kRecSlots = kPanelMaxWG + 1;   // per step: one per workgroup, one for row d
 constexpr int kTrsvMaxRhs = 32;     // left-side solves with at most this many right-hand sides
                                     // take the single-launch blocked solve
 
@@ -34,7 +37,7 @@ constexpr int kTrsvMaxRhs = 32;     // left-side solves with at most this many r
 struct DevStatus {
     int info;       // LAPACK info (first failing column, 1-based), 0 = fine
     int error;      // internal failure (e.g. a bounded wait that expired)
-    unsigned int barrier;  // cooperative-panel arrival counter
+    unsigned int barrier;  // reserved
     int pad;
 };
 
@@ -56,9 +59,6 @@ struct Ctx {
     int device = -1;
     DevStatus *dstat = nullptr;      // device status block (per device)
     DevStatus *hstat = nullptr;      // pinned host mirror
-    // cooperative panel scratch (per device)
-    double *panel_rec = nullptr;
-    size_t panel_rec_elems = 0;
     int *rowsrc = nullptr;
     size_t rowsrc_elems = 0;
     // plan mode: record instead of launch
@@ -70,13 +70,15 @@ struct Ctx {
     bool abort_on_info = false;
     // tracing: per-kernel-family event timing on the library stream
     bool trace = false;
-    unsigned int barrier_base = 0;   // running target of the panel arrival counter
     int num_cu = 256;
 };
 
 Ctx &ctx();
 void ensure_device(Ctx &c);
 void *scratch(Ctx &c, int slot, size_t bytes);   // grow-only per-device workspace
+// Exchange records of the cooperative LU panel ([kLuLeaf][kRecSlots][kRecWords]
+// words) and the first of kLuLeaf consecutive epochs reserved for one panel.
+unsigned long long *panel_records(Ctx &c, unsigned int *epoch);
 
 // Tracing hook: kernels are bracketed by events when tracing is on.
 void trace_begin(Ctx &c, int kind);

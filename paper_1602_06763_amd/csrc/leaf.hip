@@ -15,23 +15,31 @@
 namespace rl {
 
 // ---------------------------------------------------------------------------
-// potf2: unblocked Cholesky of an n×n diagonal block (n <= 64) in LDS.
+// potf2: unblocked Cholesky of an n×n diagonal block (n <= 64), one wave.
 // For uplo 'U' the block is read transposed (Uᵀ is lower) and written back
 // transposed. On a pivot that is not > 0 (or NaN) the first failing global
-// column off+k+1 is recorded in status->info, the block is written back as
-// it stands (columns before k final, a_kk unchanged) and every later kernel
-// of the call sees info != 0 and returns at once.
+// column off+k+1 is recorded in status->info, the trailing block is written
+// back as it stands (columns before k final, column k holding its updated
+// pivot) and every later kernel of the call sees info != 0 and returns at once.
+//
+// Lane r keeps row r of the not yet factored columns in registers as a
+// sliding window: x[q] is column k+q at step k, so every step addresses the
+// same registers and the step loop stays a short runtime loop. Step k
+// broadcasts column k through LDS and subtracts (a_rk / a_kk)·a_jk from
+// a_rj, which equals l_rk·l_jk and keeps the square root and the column
+// scaling off the step-to-step dependency chain; the finished column
+// l_rk = a_rk / sqrt(a_kk) is stored straight to memory.
 // ---------------------------------------------------------------------------
-// One wave; lane i keeps row i of the block in registers. Column k: the
-// diagonal comes from lane k (readlane), lanes below scale by its square root,
-// and every lane subtracts l_ik·l_jk from its entries j > k, l_jk read from
-// lane j. No LDS and no barrier: the wave runs the 64 steps in lockstep.
-__device__ __forceinline__ double readlane_val(double x, int l) {
+template <typename T>
+__device__ __forceinline__ T lane_bcast(T x, int l);
+template <>
+__device__ __forceinline__ double lane_bcast<double>(double x, int l) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
     return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ float readlane_val(float x, int l) {
+template <>
+__device__ __forceinline__ float lane_bcast<float>(float x, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
 
@@ -39,40 +47,51 @@ template <typename T>
 __global__ __launch_bounds__(64) void potf2_k(int n, T *__restrict__ A, long long lda, int upper,
                                               long long off, DevStatus *st) {
     if (st->info) return;
-    const int i = threadIdx.x;
-    T a[64];
-    // unconditional loads from clamped addresses, so all 64 are in flight together
-    const int ic = i < n ? i : n - 1;
+    __shared__ T col[128];   // column k, entries beyond 64 stay zero
+    const int r = threadIdx.x;
+    const int rc = r < n ? r : n - 1;
+    // element (i, j) of the lower factor lives at A[i + j*lda] ('L') or A[j + i*lda] ('U')
+    const long long si = upper ? lda : 1, sj = upper ? 1 : lda;
+    T x[64];
+    // every load is issued before any is used: selecting between a loaded
+    // value and zero otherwise turns into one branch and one wait per load
 #pragma unroll
-    for (int j = 0; j < 64; ++j) {
-        const int jc = j < n ? j : n - 1;
-        const T v = upper ? A[jc + (long long)ic * lda] : A[ic + (long long)jc * lda];
-        a[j] = (i < n && j <= i) ? v : T(0);
-    }
+    for (int j = 0; j < 64; ++j) x[j] = A[rc * si + (j < n ? j : n - 1) * sj];
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int j = 0; j < 64; ++j) x[j] = (r < n && j <= r) ? x[j] : T(0);
+    col[64 + r] = T(0);
     int fail = 0;
+    for (int k = 0; k < n; ++k) {
+        col[r] = x[0];
+        const T d = lane_bcast(x[0], k);
+        if (!(d > T(0))) {
+            fail = k + 1;
+            break;
+        }
+        const T rinv = T(1) / d;
+        const T t = x[0] * rinv;
+        const T lkk = sqrt(d);
+        if (r >= k && r < n) A[r * si + k * sj] = (r == k) ? lkk : x[0] / lkk;
+        // x[q] <- x[q+1] - t·col[k+1+q]; chunks past the live columns are skipped
 #pragma unroll
-    for (int k = 0; k < 64; ++k) {
-        if (k < n && !fail) {
-            const T akk = readlane_val(a[k], k);
-            if (!(akk > T(0))) {
-                fail = k + 1;
-            } else {
-                const T lkk = sqrt(akk);
-                a[k] = (i == k) ? lkk : (i > k ? a[k] / lkk : a[k]);
+        for (int c = 0; c < 8; ++c) {
+            if (8 * c < 63 - k) {
 #pragma unroll
-                for (int j = k + 1; j < 64; ++j) {
-                    const T ljk = readlane_val(a[k], j);
-                    a[j] -= a[k] * ljk;   // entries j > i are never read or stored
+                for (int u = 0; u < 8; ++u) {
+                    const int q = 8 * c + u;
+                    if (q < 63) x[q] = x[q + 1] - t * col[k + 1 + q];
                 }
             }
         }
     }
-    if (fail && i == 0) atomicCAS(&st->info, 0, (int)(off + fail));
+    if (fail) {
+        const int k = fail - 1;
+        if (r == 0) atomicCAS(&st->info, 0, (int)(off + fail));
+        if (r >= k && r < n) {
 #pragma unroll
-    for (int j = 0; j < 64; ++j) {
-        if (i < n && j <= i) {
-            if (upper) A[j + (long long)i * lda] = a[j];
-            else A[i + (long long)j * lda] = a[j];
+            for (int q = 0; q < 64; ++q)
+                if (k + q <= r) A[r * si + (long long)(k + q) * sj] = x[q];
         }
     }
 }
@@ -93,279 +112,383 @@ template void potf2<float>(Ctx &, char, int, float *, long long, long long);
 
 // ---------------------------------------------------------------------------
 // getf2 panel: partial-pivoting LU of the m_p × w panel A[c0:m, c0:c0+w]
-// (w <= 32), rows distributed over G cooperating workgroups that each keep
-// their R rows in LDS for the whole panel.
+// (w <= 32) with dgetf2's semantics (Sec. 5 keeps LAPACK's statement of the
+// problem): for column j, with d = c0 + j,
+//   - the pivot p is the first position i >= d with the largest |a_ij| (a NaN
+//     never wins; with no candidate at all, p = d); ipiv[d] = p + 1;
+//   - if a_pj != 0 (NaN counts as nonzero) rows d and p are interchanged and
+//     the column below the diagonal is divided by the pivot; otherwise info
+//     records the first such column and nothing moves;
+//   - rank-1 update of the columns right of j with row d.
 //
-// Column j (diagonal row d = c0 + j):
-//   1. each workgroup finds its largest |a_ij| over its rows i >= d (lowest
-//      row index on ties; a NaN never wins);
-//   2. if G > 1, workgroups publish (value, row, that row's w entries) and
-//      the entries of row d, then meet at a counter barrier;
-//   3. every workgroup reduces the G candidates to the pivot row p the same
-//      way, so all agree; ipiv[d] = p + 1;
-//   4. if the pivot is nonzero, rows d and p are exchanged across the panel
-//      and the column below the diagonal is divided by it; otherwise info
-//      records the first such column;
-//   5. rank-1 update of the panel columns right of j.
-// The source position of each row's content (before this panel's swaps) is
-// tracked alongside the data and written to rowsrc, so that laswp can apply
-// the panel's interchanges to the other columns with one gather.
+// Rows are spread over G cooperating workgroups of 256 threads; thread t owns
+// the rows t and t+256 of its workgroup's 512-row chunk ("contents") for the
+// whole panel and keeps the not yet factored columns of each in registers as
+// a sliding window (x[q] is column j+q at step j), so every step addresses
+// the same registers and the step loop stays a short runtime loop.
+//
+// Interchanges move no data: each content carries its current position. At
+// step j the pivot content retires to position d as row j of U, the content
+// that sat at d takes the pivot's old position, and every other live content
+// is scaled and updated. Finished entries (multipliers, and U rows) collect
+// in LDS and every content is written to its final position at the end; the
+// source row of every position goes to rowsrc so that laswp can apply the
+// panel's interchanges to the other columns with one gather.
+//
+// Workgroups exchange, per step, one record each: the key and position of
+// their best candidate and that row's window. Every 64-bit word of a record
+// carries the step's epoch in its upper half, so a reader polls exactly the
+// words it needs until their epochs match: no counter, no fence, no reset.
+// The winner is reduced identically in every workgroup, so all agree.
 // ---------------------------------------------------------------------------
-constexpr int kPanelRows = 512;           // rows per workgroup
-constexpr int kRecStride = kLuLeaf + 4;   // doubles per published record
-constexpr int kPanelStageMax = 64;        // up to this many workgroups, records are staged in LDS
-
 struct PanelArgs {
-    long long m, c0;
-    int w, G, R;
-    long long lda;
+    long long m, c0, lda;
+    int w, G;
     int *ipiv;
     int *rowsrc;
     DevStatus *st;
-    double *rec;           // [2][G+1][kRecStride]
-    unsigned int base;     // barrier counter value at entry
+    unsigned long long *rec;   // [kLuLeaf][kRecSlots][kRecWords]
+    unsigned int epoch;        // step j publishes with epoch + j
 };
 
-template <typename F, int... Js>
-__device__ __forceinline__ void static_for(F &&f, std::integer_sequence<int, Js...>) {
-    (f(std::integral_constant<int, Js>{}), ...);
-}
+constexpr int kPanelLds = kLuLeaf + 1;          // row stride of the finished-entry array
+constexpr unsigned int kPanelSpin = 1u << 22;   // poll bound per word group
 
-__device__ __forceinline__ void cand_better(double v2, long long r2, double &v1, long long &r1) {
-    if (v2 > v1 || (v2 == v1 && r2 < r1)) { v1 = v2; r1 = r2; }
-}
-
-__device__ __forceinline__ void pub(double *p, double v) {
+__device__ __forceinline__ void pubw(unsigned long long *p, unsigned long long v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ double sub(const double *p) {
+__device__ __forceinline__ unsigned long long subw(const unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Rows live in registers: thread t owns panel rows t and t+256 of its
-// workgroup's 512, all w <= 32 columns of each, so the scale and rank-1
-// update of a column are register multiply-adds. The column loop is unrolled
-// (register indices are compile-time); per-column LDS scratch is double
-// buffered by column parity, so two workgroup barriers per column suffice
-// when the panel fits one workgroup.
-//
-// Cross-workgroup exchange without cache-maintenance fences: records are
-// written and read with device-coherent atomic accesses, every writer waits
-// for its stores to complete (s_waitcnt) before the workgroup barrier, and
-// only then is the arrival counter incremented. A reader that has seen the
-// counter therefore reads complete records.
+// ---- wave-level reductions (DPP, no LDS crossbar) --------------------------
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u32(unsigned x) {
+    return (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ unsigned rlane(unsigned x, int l) { return (unsigned)__builtin_amdgcn_readlane((int)x, l); }
+// Maximum / minimum over the wave, in every lane: quad swaps, then the
+// half-row and row mirrors give each 16-lane row its extreme; the 4 rows are
+// combined from one lane of each.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned x) {
+    x = max(x, dpp_u32<0xB1>(x));   // quad_perm [1,0,3,2]
+    x = max(x, dpp_u32<0x4E>(x));   // quad_perm [2,3,0,1]
+    x = max(x, dpp_u32<0x141>(x));  // row_half_mirror
+    x = max(x, dpp_u32<0x140>(x));  // row_mirror
+    return max(max(rlane(x, 0), rlane(x, 16)), max(rlane(x, 32), rlane(x, 48)));
+}
+__device__ __forceinline__ unsigned wave_min_u32(unsigned x) {
+    x = min(x, dpp_u32<0xB1>(x));
+    x = min(x, dpp_u32<0x4E>(x));
+    x = min(x, dpp_u32<0x141>(x));
+    x = min(x, dpp_u32<0x140>(x));
+    return min(min(rlane(x, 0), rlane(x, 16)), min(rlane(x, 32), rlane(x, 48)));
+}
+// 64-bit maximum in two 32-bit passes: the high halves, then the low halves
+// of the lanes that hold the largest high half.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+    const unsigned hi = wave_max_u32((unsigned)(x >> 32));
+    const unsigned lo = wave_max_u32((unsigned)(x >> 32) == hi ? (unsigned)x : 0u);
+    return ((unsigned long long)hi << 32) | lo;
+}
+// Candidate key: 0 for "no candidate" (retired, out of range or NaN), else
+// the bit pattern of the non-negative magnitude plus one, so keys order like
+// magnitudes and key 1 is an exact zero.
+__device__ __forceinline__ unsigned long long cand_key(double mag, bool valid) {
+    return (valid && mag == mag) ? (unsigned long long)__double_as_longlong(mag) + 1ull : 0ull;
+}
+// (key, position) order of the pivot search: larger key, then lower position.
+__device__ __forceinline__ bool cand_wins(unsigned long long k2, unsigned p2, unsigned long long k1, unsigned p1) {
+    return k2 > k1 || (k2 == k1 && p2 < p1);
+}
+// The wave's winning lane (-1 if no lane has a candidate) with its key and
+// position. Positions are only compared when keys tie exactly. Uniform
+// control flow throughout (readlane).
+__device__ __forceinline__ int wave_winner(unsigned long long key, unsigned pos, unsigned long long &wk, unsigned &wp) {
+    wk = wave_max_u64(key);
+    const bool mine = key == wk && key != 0;
+    const unsigned long long ball = __ballot(mine);
+    if (ball == 0) { wp = 0xFFFFFFFFu; return -1; }
+    if (__builtin_popcountll(ball) == 1) {
+        const int wl = (int)__builtin_ctzll(ball);
+        wp = rlane(pos, wl);
+        return wl;
+    }
+    wp = wave_min_u32(mine ? pos : 0xFFFFFFFFu);
+    return (int)__builtin_ctzll(__ballot(mine && pos == wp));
+}
+
+// 32-bit chunks of a value, for epoch-tagged words
+template <typename T> struct Chunks;
+template <> struct Chunks<double> {
+    static constexpr int N = 2;
+    static __device__ __forceinline__ unsigned get(double v, int h) {
+        return h ? (unsigned)__double2hiint(v) : (unsigned)__double2loint(v);
+    }
+};
+template <> struct Chunks<float> {
+    static constexpr int N = 1;
+    static __device__ __forceinline__ unsigned get(float v, int) { return __float_as_uint(v); }
+};
+
+// Per-step LDS of the panel, double buffered by step parity: a wave that has
+// moved on to the next step never overwrites what a slower wave still reads.
+template <typename T>
+struct PanelStep {
+    T cand[4][kLuLeaf];            // window of each wave's best candidate
+    unsigned long long rk[2][4];   // [workgroup / grid reduction][wave]
+    unsigned rp[2][4];
+    int rc[2][4][2];
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArgs a) {
     constexpr int W = kLuLeaf;
-    extern __shared__ unsigned char smem_raw[];
-    double *recs = reinterpret_cast<double *>(smem_raw);  // [(G+1)][kRecStride] when staged
-    __shared__ double red_v[2][4];
-    __shared__ long long red_r[2][4];
-    __shared__ T prow[2][W];   // pivot row entries
-    __shared__ T drow[2][W];   // entries of row d before the interchange
-    __shared__ int psrc_s[2], dsrc_s[2];
-    __shared__ long long p_s[2];
+    constexpr int R = kPanelRows;
+    constexpr int NC = Chunks<T>::N;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    T *F = reinterpret_cast<T *>(smem_raw);   // multipliers [R][kPanelLds]
+    __shared__ PanelStep<T> ps[2];
+    __shared__ T Urow[W][W + 1];               // row j of U, from the step that retired it
+    __shared__ T dwin[W];                      // row d's window when it drives the update
+    __shared__ __attribute__((aligned(16))) unsigned ub[W * NC];   // pivot window from a record
+    __shared__ int abort_s;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = blockIdx.x, G = a.G, w = a.w;
-    const long long c0 = a.c0, m = a.m;
-    const long long rbeg = c0 + (long long)g * kPanelRows;
+    const long long c0 = a.c0;
+    const long long rbeg = c0 + (long long)g * R;
+    const int nr = (int)min((long long)R, a.m - rbeg);   // >= 1 for every launched workgroup
     DevStatus *st = a.st;
+    if (tid == 0) abort_s = 0;
 
-    T v[2][W];
-    int src[2];
-    long long grow[2];
+    T x[2][W];
+    unsigned pos[2];
+    int cid[2], rstep[2];
+    bool act[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        grow[k] = rbeg + tid + 256 * k;
-        const bool in = grow[k] < m;
-        const long long rc = in ? grow[k] : c0;
-        src[k] = (int)grow[k];
+        const int r = tid + 256 * k;
+        const long long rr = rbeg + min(r, nr - 1);
 #pragma unroll
-        for (int q = 0; q < W; ++q) {
-            const T x = A[rc + (c0 + (q < w ? q : 0)) * a.lda];
-            v[k][q] = (in && q < w) ? x : T(0);
+        for (int q = 0; q < W; ++q) x[k][q] = A[rr + (c0 + min(q, w - 1)) * a.lda];
+        pos[k] = (unsigned)(rbeg + r);
+        cid[k] = (int)(rbeg + r);
+        act[k] = r < nr;
+        rstep[k] = -1;
+    }
+    // all loads in flight before any is used
+    asm volatile("" ::: "memory");
+
+    for (int j = 0; j < w; ++j) {
+        PanelStep<T> &S = ps[j & 1];
+        const unsigned d = (unsigned)(c0 + j);
+        const int nw = w - j;   // live window width
+        const unsigned E = a.epoch + (unsigned)j;
+        const unsigned long long ET = (unsigned long long)E << 32;
+
+        // -- best candidate: thread, wave (its window to LDS), workgroup
+        unsigned long long key = 0;
+        unsigned kp = 0xFFFFFFFFu;
+        int kc = -1, kb = 0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const unsigned long long kk = cand_key(fabs((double)x[k][0]), act[k]);
+            if (kk != 0 && cand_wins(kk, pos[k], key, kp)) { key = kk; kp = pos[k]; kc = cid[k]; kb = k; }
+        }
+        unsigned long long wk;
+        unsigned wp;
+        const int wl = wave_winner(key, kp, wk, wp);
+        const int wc = __builtin_amdgcn_readlane(kc, wl < 0 ? 0 : wl);
+        if (lane == wl && kb == 0) {
+#pragma unroll
+            for (int q = 0; q < W; ++q) S.cand[wave][q] = x[0][q];
+        }
+        if (lane == wl && kb == 1) {
+#pragma unroll
+            for (int q = 0; q < W; ++q) S.cand[wave][q] = x[1][q];
+        }
+        if (lane == 0) {
+            S.rk[0][wave] = wk;
+            S.rp[0][wave] = wp;
+            S.rc[0][wave][0] = wl < 0 ? -1 : wc;
+            S.rc[0][wave][1] = wave;
+        }
+        __syncthreads();
+        unsigned long long bk = S.rk[0][0];
+        unsigned bp = S.rp[0][0];
+        int bc = S.rc[0][0][0], bwv = 0;
+#pragma unroll
+        for (int q = 1; q < 4; ++q)
+            if (cand_wins(S.rk[0][q], S.rp[0][q], bk, bp)) { bk = S.rk[0][q]; bp = S.rp[0][q]; bc = S.rc[0][q][0]; bwv = q; }
+
+        int src_g = -1;   // workgroup whose record holds the pivot row (G > 1)
+        if (G > 1) {
+            // publish this workgroup's candidate: one word per thread
+            unsigned long long *mine = a.rec + ((size_t)j * kRecSlots + g) * kRecWords;
+            if (tid < 4 + NC * W) {
+                unsigned v;
+                if (tid == 0) v = (unsigned)bk;
+                else if (tid == 1) v = (unsigned)(bk >> 32);
+                else if (tid == 2) v = bp;
+                else if (tid == 3) v = (unsigned)bc;
+                else v = Chunks<T>::get(S.cand[bwv][(tid - 4) / NC], (tid - 4) % NC);
+                pubw(&mine[tid], ET | v);
+            }
+            // every workgroup's header, one per thread
+            unsigned long long tk = 0;
+            unsigned tp = 0xFFFFFFFFu;
+            int tc = -1;
+            if (tid < G) {
+                const unsigned long long *rr = a.rec + ((size_t)j * kRecSlots + tid) * kRecWords;
+                unsigned long long h0, h1, h2, h3;
+                unsigned spins = 0;
+                while (true) {
+                    h0 = subw(&rr[0]); h1 = subw(&rr[1]); h2 = subw(&rr[2]); h3 = subw(&rr[3]);
+                    if ((unsigned)(h0 >> 32) == E && (unsigned)(h1 >> 32) == E && (unsigned)(h2 >> 32) == E &&
+                        (unsigned)(h3 >> 32) == E)
+                        break;
+                    if (++spins > kPanelSpin) { atomicExch(&st->error, 1); abort_s = 1; break; }
+                    if ((spins & 1023u) == 0 && __hip_atomic_load(&st->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        abort_s = 1;
+                        break;
+                    }
+                }
+                tk = ((unsigned long long)(unsigned)h1 << 32) | (unsigned)h0;
+                tp = (unsigned)h2;
+                tc = (int)(unsigned)h3;
+            }
+            // winner over the workgroups, with its content and workgroup index
+            unsigned long long gk2;
+            unsigned gp2;
+            const int gl = wave_winner(tk, tp, gk2, gp2);
+            const int gc2 = __builtin_amdgcn_readlane(tc, gl < 0 ? 0 : gl);
+            if (lane == 0) {
+                S.rk[1][wave] = gk2;
+                S.rp[1][wave] = gp2;
+                S.rc[1][wave][0] = gl < 0 ? -1 : gc2;
+                S.rc[1][wave][1] = gl < 0 ? -1 : 64 * wave + gl;
+            }
+            __syncthreads();
+            if (abort_s) return;
+            bk = S.rk[1][0]; bp = S.rp[1][0]; bc = S.rc[1][0][0]; src_g = S.rc[1][0][1];
+#pragma unroll
+            for (int q = 1; q < 4; ++q)
+                if (cand_wins(S.rk[1][q], S.rp[1][q], bk, bp)) {
+                    bk = S.rk[1][q]; bp = S.rp[1][q]; bc = S.rc[1][q][0]; src_g = S.rc[1][q][1];
+                }
+        }
+
+        // -- the pivot decision (identical in every workgroup)
+        const bool have = bk != 0;
+        const bool useD = !have || bk == 1ull;   // no candidate, or an exact zero pivot
+        const unsigned p = have ? bp : d;
+        const bool nz = !have || bk != 1ull;      // NaN at d counts as nonzero
+
+        // -- the window that drives the update: the pivot's, or row d's
+        const T *u;
+        if (G == 1) {
+            u = S.cand[bwv];
+            if (useD) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    if (act[k] && pos[k] == d) {
+#pragma unroll
+                        for (int q = 0; q < W; ++q) dwin[q] = x[k][q];
+                    }
+                }
+                __syncthreads();
+                u = dwin;
+            }
+        } else {
+            unsigned long long *srcrec =
+                a.rec + ((size_t)j * kRecSlots + (useD ? kPanelMaxWG : src_g)) * kRecWords;
+            if (useD) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    if (act[k] && pos[k] == d) {
+#pragma unroll
+                        for (int q = 0; q < W; ++q)
+#pragma unroll
+                            for (int h = 0; h < NC; ++h) pubw(&srcrec[4 + NC * q + h], ET | Chunks<T>::get(x[k][q], h));
+                    }
+                }
+            }
+            if (tid < NC * nw) {
+                unsigned long long v;
+                unsigned spins = 0;
+                while (true) {
+                    v = subw(&srcrec[4 + tid]);
+                    if ((unsigned)(v >> 32) == E) break;
+                    if (++spins > kPanelSpin) { atomicExch(&st->error, 1); abort_s = 1; break; }
+                    if ((spins & 1023u) == 0 && __hip_atomic_load(&st->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        abort_s = 1;
+                        break;
+                    }
+                }
+                ub[tid] = (unsigned)v;
+            }
+            __syncthreads();
+            if (abort_s) return;
+            u = reinterpret_cast<const T *>(ub);
+        }
+        if (g == 0 && tid == 0) {
+            a.ipiv[d] = (int)(p + 1);
+            if (!nz) atomicCAS(&st->info, 0, (int)(d + 1));
+        }
+        const T piv = u[0];
+
+        // -- retire the pivot content, move row d's, scale the rest
+        T lk[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int r = tid + 256 * k;
+            const bool ret = act[k] && (useD ? pos[k] == d : cid[k] == bc);
+            lk[k] = T(0);
+            if (ret) {
+#pragma unroll
+                for (int q = 0; q < W; ++q) Urow[j][q] = x[k][q];
+                act[k] = false;
+                pos[k] = d;
+                rstep[k] = j;
+            } else if (act[k]) {
+                if (!useD && pos[k] == d) pos[k] = p;
+                const T l = nz ? x[k][0] / piv : x[k][0];
+                F[r * kPanelLds + j] = l;
+                lk[k] = l;
+            }
+        }
+        // x[q] <- x[q+1] - l·u[q+1]; chunks past the live window are skipped
+#pragma unroll
+        for (int c = 0; c < W / 8; ++c) {
+            if (8 * c < nw - 1) {
+                T uc[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) uc[v] = (8 * c + v + 1 < W) ? u[8 * c + v + 1] : T(0);
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) {
+                        const int q = 8 * c + v;
+                        if (q < W - 1) x[k][q] = x[k][q + 1] - lk[k] * uc[v];
+                    }
+            }
         }
     }
-
-    // the column loop, unrolled at compile time so v[][] indices are constants
-    auto column = [&](auto jc) __attribute__((always_inline)) {
-        constexpr int j = decltype(jc)::value;
-        if (j < w) {
-            const int par = j & 1;
-            const long long d = c0 + j;
-            // 1. this workgroup's candidate: largest |a_ij|, rows i >= d, lowest row on ties
-            double bv = -1.0;
-            long long br = LLONG_MAX;
-#pragma unroll
-            for (int k = 0; k < 2; ++k)
-                if (grow[k] >= d && grow[k] < m) cand_better(fabs((double)v[k][j]), grow[k], bv, br);
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                const double v2 = __shfl_xor(bv, o);
-                const long long r2 = __shfl_xor(br, o);
-                cand_better(v2, r2, bv, br);
-            }
-            if (lane == 0) { red_v[par][wave] = bv; red_r[par][wave] = br; }
-            __syncthreads();
-            bv = red_v[par][0];
-            br = red_r[par][0];
-            for (int q = 1; q < 4; ++q) cand_better(red_v[par][q], red_r[par][q], bv, br);
-
-            long long p;
-            if (G == 1) {
-                p = (br == LLONG_MAX) ? d : br;
-#pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    if (grow[k] == p) {
-#pragma unroll
-                        for (int q = 0; q < W; ++q) prow[par][q] = v[k][q];
-                        psrc_s[par] = src[k];
-                    }
-                    if (grow[k] == d) {
-#pragma unroll
-                        for (int q = 0; q < W; ++q) drow[par][q] = v[k][q];
-                        dsrc_s[par] = src[k];
-                    }
-                }
-                if (tid == 0) p_s[par] = p;
-            } else {
-                // 2. publish this workgroup's candidate row (and row d), then meet
-                double *slot = a.rec + ((size_t)(j & 1) * (G + 1)) * kRecStride;
-                double *mine = slot + (size_t)g * kRecStride;
-                if (br == LLONG_MAX && tid == 0) {
-                    pub(&mine[0], -1.0);
-                    pub(&mine[1], -1.0);
-                }
-#pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    if (br != LLONG_MAX && grow[k] == br) {
-                        pub(&mine[0], bv);
-                        pub(&mine[1], (double)br);   // row indices < 2^53 are exact
-                        pub(&mine[2], (double)src[k]);
-#pragma unroll
-                        for (int q = 0; q < W; ++q) pub(&mine[4 + q], (double)v[k][q]);
-                    }
-                    if (grow[k] == d) {
-                        double *dr = slot + (size_t)G * kRecStride;
-                        pub(&dr[2], (double)src[k]);
-#pragma unroll
-                        for (int q = 0; q < W; ++q) pub(&dr[4 + q], (double)v[k][q]);
-                    }
-                }
-                __builtin_amdgcn_s_waitcnt(0);   // this thread's stores have completed
-                __syncthreads();
-                if (tid == 0) {
-                    __hip_atomic_fetch_add(&st->barrier, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const unsigned int target = a.base + (unsigned int)G * (unsigned int)(j + 1);
-                    unsigned int spins = 0;
-                    while (__hip_atomic_load(&st->barrier, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                        if (__hip_atomic_load(&st->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-                        if (++spins > (1u << 24)) {
-                            atomicExch(&st->error, 1);
-                            break;
-                        }
-                    }
-                }
-                __syncthreads();
-                // 3. reduce the G candidates in every wave (all reach the same pivot)
-                const bool staged = G <= kPanelStageMax;
-                if (staged) {
-                    // every record at once into LDS: a thread's loads are all issued
-                    // before any is used, so they share one round trip
-                    constexpr int kIt = ((kPanelStageMax + 1) * kRecStride + 255) / 256;
-                    const int nrec = (G + 1) * kRecStride;
-                    double tmp[kIt];
-#pragma unroll
-                    for (int u = 0; u < kIt; ++u) tmp[u] = sub(&slot[min(tid + u * 256, nrec - 1)]);
-#pragma unroll
-                    for (int u = 0; u < kIt; ++u) {
-                        const int e = tid + u * 256;
-                        if (e < nrec && e % kRecStride < 4 + w) recs[e] = tmp[u];
-                    }
-                    __syncthreads();
-                }
-                const double *base = staged ? recs : slot;
-                double cv = -1.0;
-                long long rr = LLONG_MAX;
-                if (staged) {
-                    for (int q = lane; q < G; q += 64) {
-                        const double cr = base[q * kRecStride + 1];
-                        if (cr >= 0.0) cand_better(base[q * kRecStride], (long long)cr, cv, rr);
-                    }
-                } else {
-                    double vv[kPanelMaxWG / 64], rv[kPanelMaxWG / 64];
-#pragma unroll
-                    for (int u = 0; u < kPanelMaxWG / 64; ++u) {
-                        const int q = min(lane + 64 * u, G - 1);
-                        vv[u] = sub(&base[q * kRecStride]);
-                        rv[u] = sub(&base[q * kRecStride + 1]);
-                    }
-#pragma unroll
-                    for (int u = 0; u < kPanelMaxWG / 64; ++u)
-                        if (lane + 64 * u < G && rv[u] >= 0.0) cand_better(vv[u], (long long)rv[u], cv, rr);
-                }
-#pragma unroll
-                for (int o = 32; o >= 1; o >>= 1) {
-                    const double v2 = __shfl_xor(cv, o);
-                    const long long r2 = __shfl_xor(rr, o);
-                    cand_better(v2, r2, cv, rr);
-                }
-                p = (rr == LLONG_MAX) ? d : rr;
-                // row d's own record also serves when d is the pivot (or no row won)
-                const double *dr = base + (size_t)G * kRecStride;
-                const double *pr = (p == d) ? dr : base + (size_t)((p - c0) / kPanelRows) * kRecStride;
-                if (tid < W) {
-                    const double x1 = staged ? pr[4 + tid] : sub(&pr[4 + tid]);
-                    const double x2 = staged ? dr[4 + tid] : sub(&dr[4 + tid]);
-                    prow[par][tid] = (T)x1;
-                    drow[par][tid] = (T)x2;
-                }
-                if (tid == 0) {
-                    psrc_s[par] = (int)(staged ? pr[2] : sub(&pr[2]));
-                    dsrc_s[par] = (int)(staged ? dr[2] : sub(&dr[2]));
-                    p_s[par] = p;
-                }
-            }
-            __syncthreads();
-            p = p_s[par];
-            if (g == 0 && tid == 0) a.ipiv[d] = (int)(p + 1);
-            const T piv = prow[par][j];
-            const bool nz = (piv != T(0));
-            if (!nz && g == 0 && tid == 0) atomicCAS(&st->info, 0, (int)(d + 1));
-            // 4+5. interchange, scale and rank-1 update, all in registers.
-            // With a zero pivot nothing moves and row d supplies the U row.
-            const T *urow = nz ? prow[par] : drow[par];
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                if (nz && grow[k] == d) {
-#pragma unroll
-                    for (int q = 0; q < W; ++q) v[k][q] = prow[par][q];
-                    src[k] = psrc_s[par];
-                } else if (nz && p != d && grow[k] == p) {
-#pragma unroll
-                    for (int q = 0; q < W; ++q) v[k][q] = drow[par][q];
-                    src[k] = dsrc_s[par];
-                }
-                if (grow[k] > d && grow[k] < m) {
-                    T l = v[k][j];
-                    if (nz) l = l / piv;
-                    v[k][j] = l;
-#pragma unroll
-                    for (int q = j + 1; q < W; ++q) v[k][q] -= l * urow[q];
-                }
-            }
-        }
-    };
-    static_for(column, std::make_integer_sequence<int, W>{});
-
+    __syncthreads();
+    // every content to its final position; the source row of each position
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        if (grow[k] < m) {
-#pragma unroll
-            for (int q = 0; q < W; ++q)
-                if (q < w) A[grow[k] + (c0 + q) * a.lda] = v[k][q];
-            a.rowsrc[grow[k]] = src[k];
+        const int r = tid + 256 * k;
+        if (r < nr) {
+            const long long fp = (long long)pos[k];
+            const int rs = rstep[k] < 0 ? W : rstep[k];
+            for (int q = 0; q < w; ++q) {
+                const T lv = F[r * kPanelLds + q];
+                const T uv = Urow[min(rs, W - 1)][max(q - rs, 0)];
+                A[fp + (c0 + q) * a.lda] = q < rs ? lv : uv;
+            }
+            a.rowsrc[fp] = cid[k];
         }
     }
 }
@@ -375,19 +498,17 @@ void getf2_panel(Ctx &c, long long m, int w, T *A, long long lda, long long c0, 
     if (plan_record(c, PK_GETF2, m - c0, w, w)) return;
     const long long mp = m - c0;
     if (mp <= 0 || w <= 0) return;
-    const int R = kPanelRows;   // two rows per thread, 256 threads
-    const int G = (int)((mp + R - 1) / R);
-    if (G > c.num_cu) { launch_error(hipErrorInvalidConfiguration); return; }
+    const int G = (int)((mp + kPanelRows - 1) / kPanelRows);
+    // every workgroup waits on every other one: all of them must be resident
+    if (G > c.num_cu || G > kPanelMaxWG) { launch_error(hipErrorInvalidConfiguration); return; }
     PanelArgs a{};
-    a.m = m; a.c0 = c0; a.w = w; a.G = G; a.R = R; a.lda = lda;
+    a.m = m; a.c0 = c0; a.lda = lda; a.w = w; a.G = G;
     a.ipiv = ipiv;
     a.rowsrc = c.rowsrc;
     a.st = c.dstat;
-    a.rec = c.panel_rec;
-    a.base = c.barrier_base;
-    if (G > 1) c.barrier_base += (unsigned int)G * (unsigned int)w;
-    const size_t shm =
-        (G > 1 && G <= kPanelStageMax) ? (size_t)(G + 1) * kRecStride * sizeof(double) : 0;
+    a.rec = panel_records(c, &a.epoch);
+    if (!a.rec) return;
+    const size_t shm = (size_t)kPanelRows * kPanelLds * sizeof(T);
     static size_t attr_bytes = 0;
     if (shm > attr_bytes) {
         RL_CHECK(hipFuncSetAttribute((const void *)getf2_panel_k<T>,

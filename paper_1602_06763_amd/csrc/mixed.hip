@@ -409,7 +409,6 @@ int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const 
     hipLaunchKernelGGL(copy_cols_k, dim3(blocks(n), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs, B, ldb, X,
                        ldx);
     hipLaunchKernelGGL(reset_info_k, dim3(1), dim3(64), 0, c.stream, c.dstat);
-    c.barrier_base = 0;  // the arrival counter was reset with the status block
     int info = 0;
     if (spd) {
         c.abort_on_info = true;

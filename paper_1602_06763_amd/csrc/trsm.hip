@@ -94,6 +94,150 @@ __global__ __launch_bounds__(256) void trsm_leaf_k(int unit, int t, const TT *__
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Matrix-core leaf: a workgroup solves N·x = b for 64 vectors (16 per wave),
+// triangle t <= 64 in LDS, blocked by 16: block I of x is
+//     x_I = N_II⁻¹ (b_I - Σ_{J before I} N_IJ·x_J),
+// the sum on the matrix cores (16×16×4 steps, vectors as columns), the 16×16
+// diagonal solve by substitution on 16 lanes (one vector each). The
+// reciprocals of the diagonal are formed once while the triangle is staged,
+// and rows beyond t are padded with the identity, so the substitution is
+// straight-line code with one multiply and one FMA on its dependency chain
+// per step. Each wave works on its own 16 vectors, so waves never wait for
+// each other after the triangle is staged.
+// ---------------------------------------------------------------------------
+template <typename TW>
+struct LeafMfma;
+template <>
+struct LeafMfma<double> {
+    typedef d4 acc_t;
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <>
+struct LeafMfma<float> {
+    typedef f4 acc_t;
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+template <typename TT, typename TB, typename TW, bool LOWER>
+__global__ __launch_bounds__(256) void trsm_leaf_mfma_k(int unit, int t, const TT *__restrict__ T, long long ti,
+                                                        long long tj, long long nvec, TB *__restrict__ B,
+                                                        long long se, long long sr, const int *abort) {
+    if (abort && *abort) return;
+    typedef LeafMfma<TW> Op;
+    typedef typename Op::acc_t acc_t;
+    __shared__ TW Nsh[64][65];
+    __shared__ TW Xsh[4][64][17];
+    __shared__ TW rdiag[64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // stage the triangle (zero outside it and beyond t): 16 unconditional loads per thread
+    {
+        TW v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
+            const bool in = i < t && j < t && (LOWER ? (j <= i) : (j >= i));
+            v[u] = (TW)T[(in ? i : 0) * ti + (in ? j : 0) * tj];
+            v[u] = in ? v[u] : TW(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
+            Nsh[i][j] = (i == j && i >= t) ? TW(1) : v[u];
+        }
+        if (tid < 64) {
+            // T(i, i) straight from memory: the staged copy is written by another thread
+            const TW dii = (TW)T[min(tid, max(t - 1, 0)) * (ti + tj)];
+            rdiag[tid] = (unit || tid >= t) ? TW(1) : TW(1) / dii;
+        }
+    }
+    // this wave's 16 vectors, element-major in LDS
+    const long long v0 = (long long)blockIdx.x * 64 + wave * 16;
+    TW (*X)[17] = Xsh[wave];
+    {
+        TW v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int e, q;
+            if (se == 1) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
+            else { q = lane & 15; e = (lane >> 4) + 4 * u; }
+            const bool in = e < t && v0 + q < nvec;
+            v[u] = (TW)B[in ? e * se + (v0 + q) * sr : 0];
+            v[u] = in ? v[u] : TW(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int e, q;
+            if (se == 1) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
+            else { q = lane & 15; e = (lane >> 4) + 4 * u; }
+            X[e][q] = v[u];
+        }
+    }
+    __syncthreads();
+
+    const int nblk = (t + 15) / 16;
+    for (int s = 0; s < nblk; ++s) {
+        const int I = LOWER ? s : nblk - 1 - s;
+        // X_I -= Σ N_IJ·X_J over the blocks already solved
+        if (s > 0) {
+            acc_t acc = acc_t{0, 0, 0, 0};
+            const int J0 = LOWER ? 0 : I + 1, J1 = LOWER ? I : nblk;
+            for (int J = J0; J < J1; ++J) {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = 16 * J + 4 * kk + (lane >> 4);
+                    acc = Op::mma(Nsh[16 * I + (lane & 15)][k], X[k][lane & 15], acc);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) X[16 * I + Op::row(lane, v)][lane & 15] -= acc[v];
+            __builtin_amdgcn_wave_barrier();
+        }
+        // diagonal 16×16 block: lanes 0..15 each finish one vector
+        if (lane < 16) {
+            TW x[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) x[i] = X[16 * I + i][lane];
+            if (LOWER) {
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const TW xj = x[j] * rdiag[16 * I + j];
+                    x[j] = xj;
+#pragma unroll
+                    for (int i = j + 1; i < 16; ++i) x[i] -= Nsh[16 * I + i][16 * I + j] * xj;
+                }
+            } else {
+#pragma unroll
+                for (int j = 15; j >= 0; --j) {
+                    const TW xj = x[j] * rdiag[16 * I + j];
+                    x[j] = xj;
+#pragma unroll
+                    for (int i = 0; i < j; ++i) x[i] -= Nsh[16 * I + i][16 * I + j] * xj;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) X[16 * I + i][lane] = x[i];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    // write the solved vectors back
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        int e, q;
+        if (se == 1) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
+        else { q = lane & 15; e = (lane >> 4) + 4 * u; }
+        if (e < t && v0 + q < nvec) B[e * se + (v0 + q) * sr] = (TB)X[e][q];
+    }
+}
+
 template <typename TT, typename TB>
 void trsm_leaf(Ctx &c, bool lower_eff, bool unit, int t, const TT *T, long long ti, long long tj,
                long long nvec, TB *B, long long se, long long sr) {
@@ -103,12 +247,14 @@ void trsm_leaf(Ctx &c, bool lower_eff, bool unit, int t, const TT *T, long long 
     const int *abort = c.abort_on_info ? &c.dstat->info : nullptr;
     trace_begin(c, PK_TRSM_LEAF);
     typedef typename std::conditional<(sizeof(TB) == 8 || sizeof(TT) == 8), double, float>::type TW;
-#define RL_LEAF(F, L)                                                                        \
-    hipLaunchKernelGGL((trsm_leaf_k<TT, TB, TW, F, L>), dim3(grid), dim3(256), 0, c.stream,    \
-                       (int)unit, t, T, ti, tj, nvec, B, se, sr, abort)
-    // the guarded form: the unguarded straight-line variant exhausts the VGPRs
-    if (lower_eff) RL_LEAF(false, true); else RL_LEAF(false, false);
-#undef RL_LEAF
+    const int grid64 = (int)((nvec + 63) / 64);
+    if (lower_eff)
+        hipLaunchKernelGGL((trsm_leaf_mfma_k<TT, TB, TW, true>), dim3(grid64), dim3(256), 0, c.stream, (int)unit, t,
+                           T, ti, tj, nvec, B, se, sr, abort);
+    else
+        hipLaunchKernelGGL((trsm_leaf_mfma_k<TT, TB, TW, false>), dim3(grid64), dim3(256), 0, c.stream, (int)unit, t,
+                           T, ti, tj, nvec, B, se, sr, abort);
+    (void)grid;
     RL_CHECK(hipGetLastError());
     trace_end(c, PK_TRSM_LEAF, (double)t * t * nvec, 8.0 * (t * t + 2.0 * t * nvec));
 }
