@@ -15,20 +15,22 @@
 namespace rl {
 
 // ---------------------------------------------------------------------------
-// potf2: unblocked Cholesky of an n×n diagonal block (n <= 64), one wave.
-// For uplo 'U' the block is read transposed (Uᵀ is lower) and written back
-// transposed. On a pivot that is not > 0 (or NaN) the first failing global
-// column off+k+1 is recorded in status->info, the trailing block is written
-// back as it stands (columns before k final, column k holding its updated
-// pivot) and every later kernel of the call sees info != 0 and returns at once.
+// potf2: Cholesky of an n×n diagonal block (n <= 64) in one workgroup, the
+// block held in LDS. For uplo 'U' the block is read transposed (Uᵀ is lower)
+// and written back transposed. On a pivot that is not > 0 (or NaN) the first
+// failing global column off+k+1 is recorded in status->info, the block is
+// written back as it stands (columns before k final, column k holding its
+// updated pivot) and every later kernel of the call sees info != 0 and
+// returns at once.
 //
-// Lane r keeps row r of the not yet factored columns in registers as a
-// sliding window: x[q] is column k+q at step k, so every step addresses the
-// same registers and the step loop stays a short runtime loop. Step k
-// broadcasts column k through LDS and subtracts (a_rk / a_kk)·a_jk from
-// a_rj, which equals l_rk·l_jk and keeps the square root and the column
-// scaling off the step-to-step dependency chain; the finished column
-// l_rk = a_rk / sqrt(a_kk) is stored straight to memory.
+// The 64 columns are taken 16 at a time, right-looking: one wave factors the
+// 16-column panel (lane = row, the panel's 16 entries of the row in
+// registers, the 16 steps unrolled so every register index is fixed), then
+// all four waves subtract the panel's contribution from the trailing lower
+// triangle on the FP64 matrix cores. A step subtracts (a_rk / a_kk)·a_jk
+// from a_rj, which equals l_rk·l_jk and keeps the square root and the column
+// scaling off the step-to-step dependency chain; the panel's columns are
+// scaled to l_rk = a_rk / sqrt(a_kk) by all waves once the panel is done.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T lane_bcast(T x, int l);
@@ -43,56 +45,133 @@ __device__ __forceinline__ float lane_bcast<float>(float x, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
 
+// C(16×16 tile at rows i0, columns j0) -= P(i0.., 16 columns from c0)·P(j0.., same)ᵀ
+// on the matrix cores; S is row-major with row stride 65.
 template <typename T>
-__global__ __launch_bounds__(64) void potf2_k(int n, T *__restrict__ A, long long lda, int upper,
-                                              long long off, DevStatus *st) {
+__device__ __forceinline__ void potf2_tile_update(T (*S)[65], int i0, int j0, int c0, int lane);
+template <>
+__device__ __forceinline__ void potf2_tile_update<double>(double (*S)[65], int i0, int j0, int c0, int lane) {
+    d4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        const int c = c0 + 4 * kk + (lane >> 4);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S[i0 + (lane & 15)][c], S[j0 + (lane & 15)][c], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[i0 + (lane >> 4) + 4 * v][j0 + (lane & 15)] -= acc[v];
+}
+template <>
+__device__ __forceinline__ void potf2_tile_update<float>(float (*S)[65], int i0, int j0, int c0, int lane) {
+    f4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        const int c = c0 + 4 * kk + (lane >> 4);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(S[i0 + (lane & 15)][c], S[j0 + (lane & 15)][c], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[i0 + 4 * (lane >> 4) + v][j0 + (lane & 15)] -= acc[v];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void potf2_k(int n, T *__restrict__ A, long long lda, int upper,
+                                               long long off, DevStatus *st) {
     if (st->info) return;
-    __shared__ T col[128];   // column k, entries beyond 64 stay zero
-    const int r = threadIdx.x;
-    const int rc = r < n ? r : n - 1;
+    __shared__ T S[64][65];
+    __shared__ T cb[2][16];
+    __shared__ T dd[16];   // pivots a_kk of the current panel
+    __shared__ int fail_s;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // element (i, j) of the lower factor lives at A[i + j*lda] ('L') or A[j + i*lda] ('U')
     const long long si = upper ? lda : 1, sj = upper ? 1 : lda;
-    T x[64];
-    // every load is issued before any is used: selecting between a loaded
-    // value and zero otherwise turns into one branch and one wait per load
+    {
+        T v[16];
 #pragma unroll
-    for (int j = 0; j < 64; ++j) x[j] = A[rc * si + (j < n ? j : n - 1) * sj];
-    asm volatile("" ::: "memory");
-#pragma unroll
-    for (int j = 0; j < 64; ++j) x[j] = (r < n && j <= r) ? x[j] : T(0);
-    col[64 + r] = T(0);
-    int fail = 0;
-    for (int k = 0; k < n; ++k) {
-        col[r] = x[0];
-        const T d = lane_bcast(x[0], k);
-        if (!(d > T(0))) {
-            fail = k + 1;
-            break;
+        for (int u = 0; u < 16; ++u) {
+            const int i = lane, j = wave + 4 * u;
+            v[u] = A[min(i, n - 1) * si + min(j, n - 1) * sj];
         }
-        const T rinv = T(1) / d;
-        const T t = x[0] * rinv;
-        const T lkk = sqrt(d);
-        if (r >= k && r < n) A[r * si + k * sj] = (r == k) ? lkk : x[0] / lkk;
-        // x[q] <- x[q+1] - t·col[k+1+q]; chunks past the live columns are skipped
+        asm volatile("" ::: "memory");
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            if (8 * c < 63 - k) {
+        for (int u = 0; u < 16; ++u) {
+            const int i = lane, j = wave + 4 * u;
+            // lower triangle; rows and columns past n are the identity
+            S[i][j] = (i < n && j < n) ? (j <= i ? v[u] : T(0)) : (i == j ? T(1) : T(0));
+        }
+    }
+    if (tid == 0) fail_s = 0;
+    __syncthreads();
+    const int nb = (n + 15) / 16;
+    for (int J = 0; J < nb; ++J) {
+        if (wave == 0) {
+            const int r = lane;
+            T x[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int q = 8 * c + u;
-                    if (q < 63) x[q] = x[q + 1] - t * col[k + 1 + q];
+            for (int q = 0; q < 16; ++q) x[q] = S[r][16 * J + q];
+            int fail = 0;
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                const int k = 16 * J + kk;
+                if (fail == 0 && k < n) {
+                    if ((r >> 4) == J) cb[kk & 1][r & 15] = x[kk];
+                    const T d = lane_bcast(x[kk], k);
+                    if (!(d > T(0))) {
+                        fail = k + 1;
+                    } else {
+                        // column kk of the panel's diagonal rows, as broadcasts
+                        T cv[16];
+#pragma unroll
+                        for (int q = kk + 1; q < 16; ++q) cv[q] = cb[kk & 1][q];
+                        const T t = x[kk] * (T(1) / d);
+                        S[r][k] = x[kk];   // a_rk; scaled by 1/sqrt(a_kk) after the panel
+                        if (r == 0) dd[kk] = d;
+#pragma unroll
+                        for (int q = kk + 1; q < 16; ++q) x[q] -= t * cv[q];
+                    }
+                }
+            }
+            if (fail) {
+                // the panel's columns from the failing one on, as they stand
+                const int k = fail - 1;
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    if (16 * J + q >= k && r >= 16 * J + q) S[r][16 * J + q] = x[q];
+                if (r == 0) fail_s = fail;
+            }
+        }
+        __syncthreads();
+        // l_rc = a_rc / sqrt(a_cc) for the panel's finished columns
+        {
+            const int fk = fail_s ? fail_s - 1 : n;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int r = lane, c = 16 * J + wave + 4 * u;
+                if (c < fk && r >= c) {
+                    const T lkk = sqrt(dd[c - 16 * J]);
+                    S[r][c] = (r == c) ? lkk : S[r][c] / lkk;
                 }
             }
         }
-    }
-    if (fail) {
-        const int k = fail - 1;
-        if (r == 0) atomicCAS(&st->info, 0, (int)(off + fail));
-        if (r >= k && r < n) {
-#pragma unroll
-            for (int q = 0; q < 64; ++q)
-                if (k + q <= r) A[r * si + (long long)(k + q) * sj] = x[q];
+        __syncthreads();
+        if (fail_s) break;
+        // trailing lower triangle: tiles (I, Jt) with J < Jt <= I < nb
+        const int m = nb - 1 - J;   // trailing tile rows
+        const int ntiles = m * (m + 1) / 2;
+        for (int tt = wave; tt < ntiles; tt += 4) {
+            // tt -> (I, Jt) in the trailing triangle
+            int I = 0, acc = 0;
+            while (acc + I + 1 <= tt) { acc += I + 1; ++I; }
+            const int Jt = tt - acc;
+            potf2_tile_update<T>(S, 16 * (J + 1 + I), 16 * (J + 1 + Jt), 16 * J, lane);
         }
+        __syncthreads();
+    }
+    const int fail = fail_s;
+    if (fail && tid == 0) atomicCAS(&st->info, 0, (int)(off + fail));
+    // write back the lower triangle
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int i = lane, j = wave + 4 * u;
+        if (i < n && j <= i) A[i * si + j * sj] = S[i][j];
     }
 }
 
@@ -101,7 +180,7 @@ void potf2(Ctx &c, char uplo, int n, T *A, long long lda, long long off) {
     if (plan_record(c, PK_POTF2, n, n, n)) return;
     if (n <= 0) return;
     trace_begin(c, PK_POTF2);
-    hipLaunchKernelGGL((potf2_k<T>), dim3(1), dim3(64), 0, c.stream, n, A, lda,
+    hipLaunchKernelGGL((potf2_k<T>), dim3(1), dim3(256), 0, c.stream, n, A, lda,
                        (int)(uplo == 'U' || uplo == 'u'), off, c.dstat);
     RL_CHECK(hipGetLastError());
     trace_end(c, PK_POTF2, (double)n * n * n / 3.0, 8.0 * n * n);
@@ -153,6 +232,7 @@ struct PanelArgs {
 
 constexpr int kPanelLds = kLuLeaf + 1;          // row stride of the finished-entry array
 constexpr unsigned int kPanelSpin = 1u << 22;   // poll bound per word group
+constexpr int kPanelStageG = 32;                // up to this many workgroups, records are read whole
 
 __device__ __forceinline__ void pubw(unsigned long long *p, unsigned long long v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -252,7 +332,10 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
     __shared__ T Urow[W][W + 1];               // row j of U, from the step that retired it
     __shared__ T dwin[W];                      // row d's window when it drives the update
     __shared__ __attribute__((aligned(16))) unsigned ub[W * NC];   // pivot window from a record
+    __shared__ __attribute__((aligned(16))) unsigned stage[kPanelStageG * kRecWords];   // records, whole
     __shared__ int abort_s;
+    __shared__ unsigned pvs[W];   // pivot position of every step
+    __shared__ int zfirst;        // first step with an exact zero pivot
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = blockIdx.x, G = a.G, w = a.w;
@@ -260,7 +343,7 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
     const long long rbeg = c0 + (long long)g * R;
     const int nr = (int)min((long long)R, a.m - rbeg);   // >= 1 for every launched workgroup
     DevStatus *st = a.st;
-    if (tid == 0) abort_s = 0;
+    if (tid == 0) { abort_s = 0; zfirst = -1; }
 
     T x[2][W];
     unsigned pos[2];
@@ -335,6 +418,55 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
                 else v = Chunks<T>::get(S.cand[bwv][(tid - 4) / NC], (tid - 4) % NC);
                 pubw(&mine[tid], ET | v);
             }
+            if (G <= kPanelStageG) {
+                // every record whole in one round trip: the headers, one word per
+                // thread, and the windows, a wave per record and a lane per word
+                const int nwin = NC * nw;
+                unsigned long long hv, wv[kPanelStageG / 4];
+                const int hg = min(tid >> 2, G - 1);
+                unsigned spins = 0;
+                while (true) {
+                    hv = subw(&a.rec[((size_t)j * kRecSlots + hg) * kRecWords + (tid & 3)]);
+#pragma unroll
+                    for (int q = 0; q < kPanelStageG / 4; ++q) {
+                        const int rg = min(wave + 4 * q, G - 1);
+                        wv[q] = subw(&a.rec[((size_t)j * kRecSlots + rg) * kRecWords + 4 + min(lane, nwin - 1)]);
+                    }
+                    bool ok = tid >= 4 * G || (unsigned)(hv >> 32) == E;
+#pragma unroll
+                    for (int q = 0; q < kPanelStageG / 4; ++q)
+                        ok = ok && (wave + 4 * q >= G || lane >= nwin || (unsigned)(wv[q] >> 32) == E);
+                    if (ok) break;
+                    if (++spins > kPanelSpin) { atomicExch(&st->error, 1); abort_s = 1; break; }
+                    if ((spins & 1023u) == 0 && __hip_atomic_load(&st->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        abort_s = 1;
+                        break;
+                    }
+                }
+                if (tid < 4 * G) stage[(tid >> 2) * kRecWords + (tid & 3)] = (unsigned)hv;
+#pragma unroll
+                for (int q = 0; q < kPanelStageG / 4; ++q)
+                    if (wave + 4 * q < G && lane < nwin) stage[(wave + 4 * q) * kRecWords + 4 + lane] = (unsigned)wv[q];
+                __syncthreads();
+                if (abort_s) return;
+                // every wave reduces the headers itself (lanes over workgroups)
+                unsigned long long tk = 0;
+                unsigned tp = 0xFFFFFFFFu;
+                int tc = -1;
+                if (lane < G) {
+                    const unsigned *h = &stage[lane * kRecWords];
+                    tk = ((unsigned long long)h[1] << 32) | h[0];
+                    tp = h[2];
+                    tc = (int)h[3];
+                }
+                unsigned long long gk2;
+                unsigned gp2;
+                const int gl = wave_winner(tk, tp, gk2, gp2);
+                bk = gk2;
+                bp = gp2;
+                bc = __builtin_amdgcn_readlane(tc, gl < 0 ? 0 : gl);
+                src_g = gl;
+            } else {
             // every workgroup's header, one per thread
             unsigned long long tk = 0;
             unsigned tp = 0xFFFFFFFFu;
@@ -377,6 +509,7 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
                 if (cand_wins(S.rk[1][q], S.rp[1][q], bk, bp)) {
                     bk = S.rk[1][q]; bp = S.rp[1][q]; bc = S.rc[1][q][0]; src_g = S.rc[1][q][1];
                 }
+            }
         }
 
         // -- the pivot decision (identical in every workgroup)
@@ -400,6 +533,8 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
                 __syncthreads();
                 u = dwin;
             }
+        } else if (G <= kPanelStageG && !useD) {
+            u = reinterpret_cast<const T *>(&stage[src_g * kRecWords + 4]);
         } else {
             unsigned long long *srcrec =
                 a.rec + ((size_t)j * kRecSlots + (useD ? kPanelMaxWG : src_g)) * kRecWords;
@@ -432,9 +567,9 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
             if (abort_s) return;
             u = reinterpret_cast<const T *>(ub);
         }
-        if (g == 0 && tid == 0) {
-            a.ipiv[d] = (int)(p + 1);
-            if (!nz) atomicCAS(&st->info, 0, (int)(d + 1));
+        if (tid == 0) {
+            pvs[j] = p;
+            if (!nz && zfirst < 0) zfirst = j;
         }
         const T piv = u[0];
 
@@ -458,24 +593,28 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
                 lk[k] = l;
             }
         }
-        // x[q] <- x[q+1] - l·u[q+1]; chunks past the live window are skipped
+        // x[q] <- x[q+1] - l·u[q+1] over the whole window: entries past the
+        // live columns are never read, and a branch here would make the
+        // compiler copy the window between registers at every step
 #pragma unroll
         for (int c = 0; c < W / 8; ++c) {
-            if (8 * c < nw - 1) {
-                T uc[8];
+            T uc[8];
 #pragma unroll
-                for (int v = 0; v < 8; ++v) uc[v] = (8 * c + v + 1 < W) ? u[8 * c + v + 1] : T(0);
+            for (int v = 0; v < 8; ++v) uc[v] = (8 * c + v + 1 < W) ? u[8 * c + v + 1] : T(0);
 #pragma unroll
-                for (int k = 0; k < 2; ++k)
+            for (int k = 0; k < 2; ++k)
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) {
-                        const int q = 8 * c + v;
-                        if (q < W - 1) x[k][q] = x[k][q + 1] - lk[k] * uc[v];
-                    }
-            }
+                for (int v = 0; v < 8; ++v) {
+                    const int q = 8 * c + v;
+                    if (q < W - 1) x[k][q] = x[k][q + 1] - lk[k] * uc[v];
+                }
         }
     }
     __syncthreads();
+    if (g == 0) {
+        if (tid < w) a.ipiv[c0 + tid] = (int)(pvs[tid] + 1);
+        if (tid == 0 && zfirst >= 0) atomicCAS(&st->info, 0, (int)(c0 + zfirst + 1));
+    }
     // every content to its final position; the source row of each position
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
