@@ -5,28 +5,38 @@ the mixed-precision + FP64-refinement solves against the FP64 solves.
 One step = the whole hot path over one synthetic input set:
   1. dpotrf (lower) of A = B·Bᵀ + n·I, then dpotrs with nrhs right-hand sides
   2. dgetrf of A ~ uniform[-1, 1], then dgetrs
-  3. dposv_mixed and dgesv_mixed (FP16 matrix-core updates, FP64 refinement to
-     eta <= 1e-14) on kappa = 1e2 test matrices with the same n
+  3. dposv_mixed and dgesv_mixed (low-precision matrix-core updates, FP64
+     refinement to eta <= 1e-14) on kappa-conditioned test matrices, same n
 Every matrix is restored from a pristine device copy before it is factored
 (untimed). ``value`` is the FP64 factorization throughput
-(n³/3 + 2n³/3) / (t_potrf + t_getrf) in TFLOP/s, timed with HIP events on the
-library stream; inputs are resident in HBM before timing starts.
+(n³/3 + 2n³/3) / (t_potrf + t_getrf) in TFLOP/s, from HIP events around each
+library call on the library stream; inputs are resident in HBM before timing
+starts. The timed steps run without per-kernel instrumentation; one more
+dpotrf + dgetrf pass right after them records HIP events around every kernel
+launch (library tracing) for the kernel-family breakdown and the roofline of
+the dominant kernel, the FP64 matrix-core GEMM on 128×128 tiles.
 
 Prints ONE JSON line. ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+``--copy-calib MB`` only runs a plain device copy of that size 20 times (the
+reference point for the HBM byte counters) and prints nothing else.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 matrix (published)
+PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 matrix (published, dense)
 PEAK_HBM = 8000.0  # GB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_k1_fp64_traffic_potrf_getrf_n16384.md")
+GEMM_SOURCES = [os.path.join(ROOT, "paper_1602_06763_amd", "csrc", f) for f in ("gemm.hip", "common.hpp")]
 
 
 def parse():
@@ -41,14 +51,37 @@ def parse():
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-n", type=int, default=5120)
+    p.add_argument("--copy-calib", type=float, default=0.0, help="MB; run only a plain device copy")
     return p.parse_args()
+
+
+def gemm_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in GEMM_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP64 GEMM family from the FETCH_SIZE /
+    WRITE_SIZE counter runs, if they were taken on the current GEMM source."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    kv = dict(re.findall(r"^\s*([a-z_0-9]+):\s*(\S+)\s*$", text, flags=re.M))
+    if kv.get("gemm_source_sha256") != gemm_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(n: int):
     """The oracle (unblocked FP64 Cholesky + partial-pivoting LU) on one n×n
     instance of each workload, on this host's cores."""
-    import numpy as np
-
     import gen
     import oracle
 
@@ -68,12 +101,26 @@ def cpu_baseline(n: int):
                       f"{t1 - t0:.1f} s + {t2 - t1:.1f} s"}
 
 
+def copy_calibration(mb: float):
+    import torch
+
+    n = int(mb * 1e6 / 8)
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(20):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_calib > 0:
+        copy_calibration(args.copy_calib)
+        return
     import numpy as np
     import torch
 
@@ -108,7 +155,7 @@ def main():
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
-    def step(record):
+    def step():
         out = {}
         A_spd.copy_(A_spd0)
         Bw.copy_(B0)
@@ -148,15 +195,22 @@ def main():
         return out
 
     for _ in range(args.warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
-    rl.trace_enable(True)
     res = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        res.append(step(True))
+        res.append(step())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+
+    # ---- one traced factorization pass: per-kernel HIP events on the library stream ----
+    A_spd.copy_(A_spd0)
+    A_ge.copy_(A_ge0)
+    torch.cuda.synchronize()
+    rl.trace_enable(True)
+    assert rl.potrf(A_spd, "L") == 0
+    assert rl.getrf(A_ge, piv) == 0
     fam = rl.trace_collect()
     rl.trace_enable(False)
 
@@ -165,16 +219,24 @@ def main():
     fl_potrf, fl_getrf = n ** 3 / 3.0, 2.0 * n ** 3 / 3.0
     value = (fl_potrf + fl_getrf) / ((t_potrf + t_getrf) * 1e-3) / 1e12
 
-    # dominant kernel: the FP64 matrix-core GEMM family (trailing updates)
-    dom_name = max(("gemm", "syrk"), key=lambda k: fam.get(k, {}).get("ms", 0.0))
-    d = fam.get(dom_name, {"launches": 0, "ms": 0.0, "flops": 0.0})
-    achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
+    # dominant kernel: the FP64 matrix-core GEMM on 128×128 tiles (the
+    # recursion's large Schur-complement updates; the smaller-tile launches
+    # are the "gemm" family)
+    d = fam.get("gemm128", {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0})
+    launches = max(d["launches"], 1)
+    avg_s = d["ms"] * 1e-3 / launches
+    achieved = (d["flops"] / launches) / avg_s / 1e12 if d["ms"] > 0 else 0.0
+    traffic = measured_traffic()
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64, 4), "traffic": None,
-                "kernel": f"gemm_k1 FP64 ({dom_name})", "launches": d["launches"],
-                "avg_launch_us": round(d["ms"] * 1e3 / max(d["launches"], 1), 3)}
-    families = {k: {"launches": v["launches"] // max(args.steps, 1),
-                    "ms_per_step": round(v["ms"] / max(args.steps, 1), 3),
+                "frac": round(achieved / PEAK_FP64, 4),
+                "traffic": round(traffic, 1) if traffic is not None else None,
+                "kernel": "gemm_k1<double,...,TRI=0,128,128> (FP64 GEMM, 128x128 tiles)",
+                "launches": d["launches"], "avg_launch_us": round(avg_s * 1e6, 3),
+                "flops_per_launch": round(d["flops"] / launches, 1),
+                "algorithmic_bytes_per_launch": round(d["bytes"] / launches, 1)}
+    families = {k: {"launches": v["launches"],
+                    "ms": round(v["ms"], 3),
+                    "avg_us": round(v["ms"] * 1e3 / max(v["launches"], 1), 2),
                     "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) if v["ms"] > 0 and v["flops"] > 0 else None,
                     "gbps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 and v["bytes"] > 0 else None}
                 for k, v in fam.items()}
@@ -203,7 +265,7 @@ def main():
         "getrs_ms": round(med("getrs"), 3),
         "frac_of_fp64_peak": round(value / PEAK_FP64, 4),
         "roofline": roofline,
-        "kernel_families": families,
+        "kernel_families_one_pass": families,
         "input_build_s": round(t_gen, 1),
     }
     if mixed:

@@ -187,9 +187,12 @@ void relapack_trace_enable(int on);
 
 /* Per kernel family k in [0, cap): out[4k .. 4k+3] = {launches, total ms,
  * algorithmic flops, algorithmic bytes}; families: 1 potf2, 2 trsm leaf,
- * 3 gemm, 4 syrk (FP64 matrix cores), 5 getf2 panel, 6 laswp, 7 convert,
- * 8 residual, 10 gemm and 11 syrk with FP32/FP16/BF16 operands. Synchronizes
- * the stream and clears the records. Returns cap, or -1 on a HIP error. */
+ * 3 gemm on 64×64 tiles and 12 gemm on 128×128 tiles, 4 syrk (FP64 matrix
+ * cores), 5 getf2 panel, 6 laswp, 7 convert, 8 residual, 10 gemm and 11 syrk
+ * with FP32/FP16/BF16 operands. Single-kernel families are timed by the
+ * kernel's own start/end timestamps, the others by events around them.
+ * Synchronizes the stream and clears the records. Returns cap, or -1 on a
+ * HIP error. */
 int relapack_trace_collect(double *out, int cap);
 
 /* The kernel-call sequence of one factorization without launching anything

@@ -54,7 +54,7 @@ _SIGS = {
 }
 
 TRACE_FAMILIES = {1: "potf2", 2: "trsm_leaf", 3: "gemm", 4: "syrk", 5: "getf2_panel", 6: "laswp",
-                  7: "convert", 8: "residual", 10: "gemm_lowprec", 11: "syrk_lowprec"}
+                  7: "convert", 8: "residual", 10: "gemm_lowprec", 11: "syrk_lowprec", 12: "gemm128"}
 
 PREC = {"fp32": 32, "32": 32, 32: 32, "fp16": 16, "16": 16, 16: 16, "bf16": ord("b"), "b": ord("b")}
 

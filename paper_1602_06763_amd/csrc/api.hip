@@ -216,6 +216,30 @@ void trace_end(Ctx &c, int kind, double flops, double bytes) {
     t_trace.push_back(TraceRec{kind, flops, bytes, e0, e1});
 }
 
+void trace_kernel_begin(Ctx &c) {
+    c.tev_armed = false;
+    c.tev_used = false;
+    if (!c.trace || c.plan) return;
+    if (t_evused + 2 > t_evpool.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            RL_CHECK(hipEventCreate(&e));
+            t_evpool.push_back(e);
+        }
+    }
+    c.tev0 = t_evpool[t_evused];
+    c.tev1 = t_evpool[t_evused + 1];
+    c.tev_armed = true;
+}
+
+void trace_kernel_end(Ctx &c, int kind, double flops, double bytes) {
+    c.tev_armed = false;
+    if (!c.trace || c.plan || !c.tev_used) return;
+    c.tev_used = false;
+    t_trace.push_back(TraceRec{kind, flops, bytes, t_evpool[t_evused], t_evpool[t_evused + 1]});
+    t_evused += 2;
+}
+
 // Begin / end of one library call.
 static bool call_begin(Ctx &c, bool abort_on_info) {
     t_err = 0;

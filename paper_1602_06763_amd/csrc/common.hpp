@@ -5,6 +5,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstddef>
 #include <cstdint>
@@ -50,7 +51,8 @@ struct PlanRec {
 
 enum PlanKind : int {
     PK_POTF2 = 1, PK_TRSM_LEAF = 2, PK_GEMM = 3, PK_SYRK = 4, PK_GETF2 = 5, PK_LASWP = 6,
-    PK_CONVERT = 7, PK_RESID = 8, PK_OTHER = 9, PK_GEMM_LP = 10, PK_SYRK_LP = 11
+    PK_CONVERT = 7, PK_RESID = 8, PK_OTHER = 9, PK_GEMM_LP = 10, PK_SYRK_LP = 11,
+    PK_GEMM_BIG = 12   // FP64 GEMM launches on 128×128 tiles (traced separately from PK_GEMM)
 };
 
 // Per-thread library state: stream, plan recording, tracing.
@@ -70,6 +72,8 @@ struct Ctx {
     bool abort_on_info = false;
     // tracing: per-kernel-family event timing on the library stream
     bool trace = false;
+    hipEvent_t tev0 = nullptr, tev1 = nullptr;   // armed pair for the next launch
+    bool tev_armed = false, tev_used = false;
     int num_cu = 256;
 };
 
@@ -80,9 +84,26 @@ void *scratch(Ctx &c, int slot, size_t bytes);   // grow-only per-device workspa
 // words) and the first of kLuLeaf consecutive epochs reserved for one panel.
 unsigned long long *panel_records(Ctx &c, unsigned int *epoch);
 
-// Tracing hook: kernels are bracketed by events when tracing is on.
+// Tracing hooks. A region of several launches is bracketed by events recorded
+// on the stream (trace_begin / trace_end); a single launch through rl_launch
+// between trace_kernel_begin / trace_kernel_end is timed by the launch itself
+// (the kernel's own start and end timestamps).
 void trace_begin(Ctx &c, int kind);
 void trace_end(Ctx &c, int kind, double flops, double bytes);
+void trace_kernel_begin(Ctx &c);
+void trace_kernel_end(Ctx &c, int kind, double flops, double bytes);
+
+template <typename F, typename... Args>
+inline void rl_launch(Ctx &c, F kernel, dim3 grid, dim3 block, unsigned shm, Args... args) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c.tev_armed) {
+        e0 = c.tev0;
+        e1 = c.tev1;
+        c.tev_armed = false;
+        c.tev_used = true;
+    }
+    hipExtLaunchKernelGGL(kernel, grid, block, shm, c.stream, e0, e1, 0u, args...);
+}
 
 inline bool plan_record(Ctx &c, int kind, long long m, long long n, long long k) {
     if (!c.plan) return false;

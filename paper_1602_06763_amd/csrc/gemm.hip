@@ -244,8 +244,7 @@ static void launch_k1(Ctx &c, const GemmArgs<TA, TB, TC> &args0) {
     a.ntiles = TRI ? a.tiles_m * (a.tiles_m + 1) / 2 : a.tiles_m * a.tiles_n;
     if (a.ntiles <= 0) return;
     const int grid = (a.ntiles + 7) / 8 * 8;
-    hipLaunchKernelGGL((gemm_k1<TL, TA, TB, TC, TRA, TRB, TRI, BM, BM>), dim3(grid), dim3(256), 0,
-                       c.stream, a);
+    rl_launch(c, gemm_k1<TL, TA, TB, TC, TRA, TRB, TRI, BM, BM>, dim3(grid), dim3(256), 0, a);
     RL_CHECK(hipGetLastError());
 }
 
@@ -445,7 +444,7 @@ static void launch_k8(Ctx &c, const GemmArgs<float, float, float> &args0) {
     a.ntiles = TRI ? a.tiles_m * (a.tiles_m + 1) / 2 : a.tiles_m * a.tiles_n;
     if (a.ntiles <= 0) return;
     const int grid = (a.ntiles + 7) / 8 * 8;
-    hipLaunchKernelGGL((gemm_k8<H, TRA, TRB, TRI, BM>), dim3(grid), dim3(256), 0, c.stream, a);
+    rl_launch(c, gemm_k8<H, TRA, TRB, TRI, BM>, dim3(grid), dim3(256), 0, a);
     RL_CHECK(hipGetLastError());
 }
 
@@ -490,14 +489,17 @@ void gemm(Ctx &c, Mfma mode, char ta, char tb, char tri, long long m, long long 
     a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc;
     a.abort = c.dstat ? &c.dstat->info : nullptr;
     if (!c.abort_on_info) a.abort = nullptr;
-    const int kind = mode == Mfma::F64 ? (tri ? PK_SYRK : PK_GEMM) : (tri ? PK_SYRK_LP : PK_GEMM_LP);
-    trace_begin(c, kind);
+    // the launch below picks 128×128 tiles exactly when this holds
+    const bool big = ((m + 127) / 128) * ((n + 127) / 128) / (tri ? 2 : 1) >= 2LL * c.num_cu;
+    const int kind = mode == Mfma::F64 ? (tri ? PK_SYRK : (big ? PK_GEMM_BIG : PK_GEMM))
+                                       : (tri ? PK_SYRK_LP : PK_GEMM_LP);
+    trace_kernel_begin(c);
     if (mode == Mfma::F64) dispatch<double>(c, ta, tb, tri, a);
     else if (mode == Mfma::F32) dispatch<float>(c, ta, tb, tri, a);
     else dispatch_half(c, mode, ta, tb, tri, a);
     const double bytes = (double)sizeof(TA) * m * k + (double)sizeof(TB) * k * n +
                          2.0 * sizeof(TC) * m * n / (tri ? 2.0 : 1.0);
-    trace_end(c, kind, flops, bytes);
+    trace_kernel_end(c, kind, flops, bytes);
 }
 
 template void gemm<double, double, double>(Ctx &, Mfma, char, char, char, long long, long long,

@@ -179,11 +179,10 @@ template <typename T>
 void potf2(Ctx &c, char uplo, int n, T *A, long long lda, long long off) {
     if (plan_record(c, PK_POTF2, n, n, n)) return;
     if (n <= 0) return;
-    trace_begin(c, PK_POTF2);
-    hipLaunchKernelGGL((potf2_k<T>), dim3(1), dim3(256), 0, c.stream, n, A, lda,
-                       (int)(uplo == 'U' || uplo == 'u'), off, c.dstat);
+    trace_kernel_begin(c);
+    rl_launch(c, potf2_k<T>, dim3(1), dim3(256), 0, n, A, lda, (int)(uplo == 'U' || uplo == 'u'), off, c.dstat);
     RL_CHECK(hipGetLastError());
-    trace_end(c, PK_POTF2, (double)n * n * n / 3.0, 8.0 * n * n);
+    trace_kernel_end(c, PK_POTF2, (double)n * n * n / 3.0, 8.0 * n * n);
 }
 
 template void potf2<double>(Ctx &, char, int, double *, long long, long long);
@@ -654,10 +653,10 @@ void getf2_panel(Ctx &c, long long m, int w, T *A, long long lda, long long c0, 
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
         attr_bytes = shm;
     }
-    trace_begin(c, PK_GETF2);
-    hipLaunchKernelGGL((getf2_panel_k<T>), dim3(G), dim3(256), shm, c.stream, A, a);
+    trace_kernel_begin(c);
+    rl_launch(c, getf2_panel_k<T>, dim3(G), dim3(256), (unsigned)shm, A, a);
     RL_CHECK(hipGetLastError());
-    trace_end(c, PK_GETF2, (double)mp * w * w, 2.0 * sizeof(T) * mp * w);
+    trace_kernel_end(c, PK_GETF2, (double)mp * w * w, 2.0 * sizeof(T) * mp * w);
 }
 
 template void getf2_panel<double>(Ctx &, long long, int, double *, long long, long long, int *);
@@ -714,11 +713,11 @@ void laswp_leaf(Ctx &c, long long ncols_total, T *A, long long lda, long long k0
     if (others <= 0 || w <= 0) return;
     (void)m;
     const int grid = (int)((others + 31) / 32);
-    trace_begin(c, PK_LASWP);
-    hipLaunchKernelGGL((laswp_leaf_k<T>), dim3(grid), dim3(256), 0, c.stream, A, lda, k0, w, ipiv,
-                       c.rowsrc, ncols_total, (const int *)nullptr);
+    trace_kernel_begin(c);
+    rl_launch(c, laswp_leaf_k<T>, dim3(grid), dim3(256), 0, A, lda, k0, w, ipiv, (const int *)c.rowsrc,
+              ncols_total, (const int *)nullptr);
     RL_CHECK(hipGetLastError());
-    trace_end(c, PK_LASWP, 0.0, 4.0 * sizeof(T) * w * others);
+    trace_kernel_end(c, PK_LASWP, 0.0, 4.0 * sizeof(T) * w * others);
 }
 
 template void laswp_leaf<double>(Ctx &, long long, double *, long long, long long, int, long long,

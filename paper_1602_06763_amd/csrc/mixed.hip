@@ -293,13 +293,72 @@ static Mfma prec_mode(int prec) {
 }
 
 // R = B - Af·X, eta per column, returns max eta (one 8-byte read-back)
+// R = B - A·X in FP64 for a few right-hand sides (the residual of an IR
+// sweep is a matrix-vector product, bound by reading A once from HBM): a
+// workgroup per 64 rows, its four waves splitting the columns, lane = row so
+// every load of A is a coalesced 512-byte column segment; 16 columns are in
+// flight per wave.
+constexpr int kResidMaxRhs = 4;
+template <int NR>
+__global__ __launch_bounds__(256) void resid_k(long long n, const double *__restrict__ A, long long lda,
+                                               const double *__restrict__ X, long long ldx,
+                                               const double *__restrict__ B, long long ldb, double *__restrict__ R,
+                                               long long ldr) {
+    __shared__ double part[4][NR][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long row = (long long)blockIdx.x * 64 + lane;
+    const long long rc = row < n ? row : n - 1;
+    const long long per = (n + 3) / 4;
+    const long long j0 = wave * per, j1 = min(n, j0 + per);
+    double acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+    long long j = j0;
+    for (; j + 16 <= j1; j += 16) {
+        double a[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) a[u] = A[rc + (j + u) * lda];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[r] = fma(a[u], X[(j + u) + r * ldx], acc[r]);
+    }
+    for (; j < j1; ++j) {
+        const double a = A[rc + j * lda];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] = fma(a, X[j + r * ldx], acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) part[wave][r][lane] = acc[r];
+    __syncthreads();
+    if (wave == 0 && row < n) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            R[row + r * ldr] = B[row + r * ldb] - ((part[0][r][lane] + part[1][r][lane]) + (part[2][r][lane] + part[3][r][lane]));
+    }
+}
+
 static double residual_eta(Ctx &c, long long n, long long nrhs, MixedWork &w, const double *B, long long ldb,
                            const double *X, long long ldx) {
-    trace_begin(c, PK_RESID);
-    hipLaunchKernelGGL(copy_cols_k, dim3(blocks(n), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs, B, ldb,
-                       w.R, n);
-    trace_end(c, PK_RESID, 0.0, 16.0 * n * nrhs);
-    gemm<double, double, double>(c, Mfma::F64, 'N', 'N', 0, n, nrhs, n, -1.0, w.Af, w.ldaf, X, ldx, 1.0, w.R, n);
+    if (nrhs <= kResidMaxRhs) {
+        trace_begin(c, PK_RESID);
+        const dim3 g((unsigned)((n + 63) / 64));
+        if (nrhs == 1)
+            hipLaunchKernelGGL(resid_k<1>, g, dim3(256), 0, c.stream, n, w.Af, w.ldaf, X, ldx, B, ldb, w.R, n);
+        else if (nrhs == 2)
+            hipLaunchKernelGGL(resid_k<2>, g, dim3(256), 0, c.stream, n, w.Af, w.ldaf, X, ldx, B, ldb, w.R, n);
+        else
+            for (long long r0 = 0; r0 < nrhs; r0 += 1)
+                hipLaunchKernelGGL(resid_k<1>, g, dim3(256), 0, c.stream, n, w.Af, w.ldaf, X + r0 * ldx, ldx,
+                                   B + r0 * ldb, ldb, w.R + r0 * n, n);
+        trace_end(c, PK_RESID, 2.0 * n * n * nrhs, 8.0 * n * n + 24.0 * n * nrhs);
+    } else {
+        trace_begin(c, PK_RESID);
+        hipLaunchKernelGGL(copy_cols_k, dim3(blocks(n), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs, B, ldb,
+                           w.R, n);
+        trace_end(c, PK_RESID, 0.0, 16.0 * n * nrhs);
+        gemm<double, double, double>(c, Mfma::F64, 'N', 'N', 0, n, nrhs, n, -1.0, w.Af, w.ldaf, X, ldx, 1.0, w.R, n);
+    }
     hipLaunchKernelGGL(col_eta_k, dim3((unsigned)nrhs), dim3(256), 0, c.stream, n, w.R, n, X, ldx, B, ldb,
                        w.scal, w.eta);
     hipLaunchKernelGGL(max_of_k, dim3(1), dim3(256), 0, c.stream, nrhs, w.eta, w.scal + 1);

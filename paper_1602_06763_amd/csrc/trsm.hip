@@ -245,18 +245,18 @@ void trsm_leaf(Ctx &c, bool lower_eff, bool unit, int t, const TT *T, long long 
     if (t <= 0 || nvec <= 0) return;
     const int grid = (int)((nvec + 255) / 256);
     const int *abort = c.abort_on_info ? &c.dstat->info : nullptr;
-    trace_begin(c, PK_TRSM_LEAF);
+    trace_kernel_begin(c);
     typedef typename std::conditional<(sizeof(TB) == 8 || sizeof(TT) == 8), double, float>::type TW;
     const int grid64 = (int)((nvec + 63) / 64);
     if (lower_eff)
-        hipLaunchKernelGGL((trsm_leaf_mfma_k<TT, TB, TW, true>), dim3(grid64), dim3(256), 0, c.stream, (int)unit, t,
-                           T, ti, tj, nvec, B, se, sr, abort);
+        rl_launch(c, trsm_leaf_mfma_k<TT, TB, TW, true>, dim3(grid64), dim3(256), 0, (int)unit, t, T, ti, tj, nvec, B,
+                  se, sr, abort);
     else
-        hipLaunchKernelGGL((trsm_leaf_mfma_k<TT, TB, TW, false>), dim3(grid64), dim3(256), 0, c.stream, (int)unit, t,
-                           T, ti, tj, nvec, B, se, sr, abort);
+        rl_launch(c, trsm_leaf_mfma_k<TT, TB, TW, false>, dim3(grid64), dim3(256), 0, (int)unit, t, T, ti, tj, nvec,
+                  B, se, sr, abort);
     (void)grid;
     RL_CHECK(hipGetLastError());
-    trace_end(c, PK_TRSM_LEAF, (double)t * t * nvec, 8.0 * (t * t + 2.0 * t * nvec));
+    trace_kernel_end(c, PK_TRSM_LEAF, (double)t * t * nvec, 8.0 * (t * t + 2.0 * t * nvec));
 }
 
 
