@@ -27,13 +27,11 @@ struct DevState {
     size_t slot_bytes[kScratchSlots] = {};
     int num_cu = 256;
     // single-launch triangular solve
-    double *trsv_x = nullptr;
+    unsigned long long *trsv_x = nullptr;   // epoch-tagged solution words
     size_t trsv_x_rows = 0;
-    int *trsv_ready = nullptr;
-    int trsv_ready_n = 0;
     unsigned long long *trsv_ticket = nullptr;
     unsigned long long trsv_tickets = 0;
-    int trsv_epoch = 0;
+    unsigned int trsv_epoch = 0;
 };
 
 DevState g_dev[kMaxDev];
@@ -155,43 +153,34 @@ unsigned long long *panel_records(Ctx &c, unsigned int *epoch) {
 
 TrsvWork trsv_work(Ctx &c, long long m, int nb, int launches) {
     TrsvWork w;
+    (void)nb;
     std::lock_guard<std::mutex> lk(g_mu);
     DevState &d = g_dev[c.device];
     if (d.trsv_x_rows < (size_t)m) {
         if (d.trsv_x) { RL_CHECK(hipStreamSynchronize(c.stream)); RL_CHECK(hipFree(d.trsv_x)); }
         d.trsv_x = nullptr;
-        if (hipMalloc(&d.trsv_x, (size_t)m * 8 * sizeof(double)) != hipSuccess) {
+        const long long words = m * 16;
+        if (hipMalloc(&d.trsv_x, (size_t)words * sizeof(unsigned long long)) != hipSuccess) {
             d.trsv_x_rows = 0;
             launch_error(hipErrorOutOfMemory);
             return w;
         }
+        // epochs start at 1, so zeroed words never match
+        hipLaunchKernelGGL(fill_u64_k, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, c.stream, d.trsv_x,
+                           words, 0ull);
         d.trsv_x_rows = (size_t)m;
-    }
-    if (d.trsv_ready_n < nb) {
-        if (d.trsv_ready) { RL_CHECK(hipStreamSynchronize(c.stream)); RL_CHECK(hipFree(d.trsv_ready)); }
-        d.trsv_ready = nullptr;
-        if (hipMalloc(&d.trsv_ready, (size_t)nb * sizeof(int)) != hipSuccess) {
-            d.trsv_ready_n = 0;
-            launch_error(hipErrorOutOfMemory);
-            return w;
-        }
-        // epochs start at 1, so a fresh array (all 0) reads as "not ready"
-        hipLaunchKernelGGL(fill_int_k, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, c.stream, d.trsv_ready,
-                           (long long)nb, 0);
-        d.trsv_ready_n = nb;
     }
     if (!d.trsv_ticket) {
         RL_CHECK(hipMalloc(&d.trsv_ticket, sizeof(unsigned long long)));
         hipLaunchKernelGGL(zero_u64_one_k, dim3(1), dim3(64), 0, c.stream, d.trsv_ticket);
         d.trsv_tickets = 0;
     }
-    w.xbuf = d.trsv_x;
-    w.ready = d.trsv_ready;
+    w.xw = d.trsv_x;
     w.ticket = d.trsv_ticket;
     w.ticket_base = d.trsv_tickets;
     w.epoch = d.trsv_epoch + 1;
     d.trsv_tickets += (unsigned long long)nb * (unsigned long long)launches;
-    d.trsv_epoch += launches;
+    d.trsv_epoch += (unsigned)launches;
     return w;
 }
 
@@ -293,7 +282,6 @@ void relapack_finalize(void) {
         if (d.panel_rec) (void)hipFree(d.panel_rec);
         if (d.rowsrc) (void)hipFree(d.rowsrc);
         if (d.trsv_x) (void)hipFree(d.trsv_x);
-        if (d.trsv_ready) (void)hipFree(d.trsv_ready);
         if (d.trsv_ticket) (void)hipFree(d.trsv_ticket);
         for (int s = 0; s < kScratchSlots; ++s)
             if (d.slot[s]) (void)hipFree(d.slot[s]);

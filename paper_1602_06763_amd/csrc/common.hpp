@@ -172,14 +172,14 @@ inline long long split_size(long long n, long long quantum = kSplitQuantum) {
 
 int launch_error(hipError_t e);
 
-// Workspace of the single-launch triangular solve: ticket counter, per-block
-// ready flags (compared against a per-launch epoch) and published solutions.
+// Workspace of the single-launch triangular solve: ticket counter and the
+// published solutions as epoch-tagged 64-bit words ([m][8][2]; a fresh buffer
+// is zeroed and epochs start at 1).
 struct TrsvWork {
-    double *xbuf = nullptr;
-    int *ready = nullptr;
+    unsigned long long *xw = nullptr;
     unsigned long long *ticket = nullptr;
     unsigned long long ticket_base = 0;
-    int epoch = 0;
+    unsigned int epoch = 0;
 };
 // Reserves ticket and epoch ranges for ceil(nrhs/8) launches of nb blocks.
 TrsvWork trsv_work(Ctx &c, long long m, int nb, int launches = 4);  // records a HIP failure in the calling thread's state

@@ -15,7 +15,7 @@
 
 namespace rl {
 
-enum ScratchSlot { SL_LP = 0, SL_FULL = 1, SL_VEC = 2, SL_RED = 3, SL_FB = 4, SL_PIV = 5 };
+enum ScratchSlot { SL_LP = 0, SL_FULL = 1, SL_VEC = 2, SL_RED = 3, SL_FB = 4, SL_PIV = 5, SL_PERM = 6 };
 
 __global__ void reset_info_k(DevStatus *s) {
     if (threadIdx.x == 0) { s->info = 0; s->error = 0; s->barrier = 0u; }
@@ -271,6 +271,7 @@ struct MixedWork {
     double *scal = nullptr;                // [0] ||A||inf, [1] max eta
     double *part = nullptr;                // row-sum partials
     int *ipiv = nullptr;
+    int *perm = nullptr;                   // general: the pivots as a gather map
 };
 
 static double fetch_scalar(Ctx &c, const double *dptr) {
@@ -374,11 +375,55 @@ static void inf_norm(Ctx &c, long long n, const double *A, long long lda, MixedW
     RL_CHECK(hipGetLastError());
 }
 
+// The row permutation of a partial-pivoting factorization as a gather map:
+// perm[i] is the row of the original matrix that ends up in row i after the
+// interchanges ipiv[0..n) are applied in order. One workgroup; the sequential
+// interchanges run on LDS copies when they fit, else on the output array.
+__global__ __launch_bounds__(256) void ipiv_to_perm_k(long long n, const int *__restrict__ ipiv, int *perm) {
+    extern __shared__ int pl[];   // [2n] perm, ipiv (when they fit)
+    const bool lds = n <= 16384;
+    int *P = lds ? pl : perm;
+    for (long long i = threadIdx.x; i < n; i += 256) {
+        P[i] = (int)i;
+        if (lds) pl[n + i] = ipiv[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (long long k = 0; k < n; ++k) {
+            const long long p = (lds ? pl[n + k] : ipiv[k]) - 1;
+            if (p != k) {
+                const int t = P[k];
+                P[k] = P[p];
+                P[p] = t;
+            }
+        }
+    }
+    __syncthreads();
+    if (lds)
+        for (long long i = threadIdx.x; i < n; i += 256) perm[i] = pl[i];
+}
+
+// D(i, :) = s(perm[i]) · R(perm[i], :): the row scaling and the interchanges
+// of the general correction solve in one gather.
+__global__ void perm_scale_rows_k(long long n, long long ncol, const int *__restrict__ perm, const double *s,
+                                  const double *R, long long ldr, double *D, long long ldd) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long c = blockIdx.y;
+    if (i < n) {
+        const long long p = perm[i];
+        D[i + c * ldd] = s[p] * R[p + c * ldr];
+    }
+}
+
 // D = A_lp⁻¹·R through the scaled low-precision factors, in FP64 arithmetic
 static void correction(Ctx &c, bool spd, char uplo, long long n, long long nrhs, MixedWork &w) {
     const dim3 g(blocks(n), (unsigned)nrhs);
-    // D = s1 ∘ R   (SPD: D·r;  general: R·r)
-    hipLaunchKernelGGL(scale_rows_k, g, dim3(256), 0, c.stream, n, nrhs, (const double *)w.s1, w.R, n, w.D, n);
+    // D = s1 ∘ R (SPD: D·r), or P·(s1 ∘ R) (general: P·R·r) in one gather
+    if (spd)
+        hipLaunchKernelGGL(scale_rows_k, g, dim3(256), 0, c.stream, n, nrhs, (const double *)w.s1, w.R, n, w.D, n);
+    else
+        hipLaunchKernelGGL(perm_scale_rows_k, g, dim3(256), 0, c.stream, n, nrhs, (const int *)w.perm,
+                           (const double *)w.s1, (const double *)w.R, n, w.D, n);
     if (spd) {
         if (uplo == 'L') {
             trsm<float, double>(c, Mfma::F64, 'L', 'L', 'N', 'N', n, nrhs, w.S, n, w.D, n);
@@ -388,7 +433,6 @@ static void correction(Ctx &c, bool spd, char uplo, long long n, long long nrhs,
             trsm<float, double>(c, Mfma::F64, 'L', 'U', 'N', 'N', n, nrhs, w.S, n, w.D, n);
         }
     } else {
-        laswp_rows<double>(c, nrhs, w.D, n, w.ipiv, 0, n, false);
         trsm<float, double>(c, Mfma::F64, 'L', 'L', 'N', 'U', n, nrhs, w.S, n, w.D, n);
         trsm<float, double>(c, Mfma::F64, 'L', 'U', 'N', 'N', n, nrhs, w.S, n, w.D, n);
     }
@@ -429,6 +473,20 @@ int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const 
     if (spd) potrf_rec<float>(c, mode, uplo, n, w.S, n, 0);
     else getrf_top<float>(c, mode, n, n, w.S, n, w.ipiv);
     c.abort_on_info = false;
+    if (!spd) {
+        w.perm = (int *)scratch(c, SL_PERM, (size_t)n * sizeof(int));
+        if (!w.perm) return -1000 - (int)hipErrorOutOfMemory;
+        const size_t shm = n <= 16384 ? (size_t)2 * n * sizeof(int) : 0;
+        static size_t attr = 0;
+        if (shm > attr) {
+            RL_CHECK(hipFuncSetAttribute((const void *)ipiv_to_perm_k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)shm));
+            attr = shm;
+        }
+        hipLaunchKernelGGL(ipiv_to_perm_k, dim3(1), dim3(256), (unsigned)shm, c.stream, n, (const int *)w.ipiv,
+                           w.perm);
+        RL_CHECK(hipGetLastError());
+    }
     const int lp_info = fetch_info(c);
     int status = 0;  // 0 running, 1 converged, -3 lp failed, -31 stalled
     double eta = INFINITY;

@@ -264,24 +264,30 @@ void trsm_leaf(Ctx &c, bool lower_eff, bool unit, int t, const TT *T, long long 
 // Blocked triangular solve for a few right-hand sides (nrhs <= 8 per launch):
 // one launch for the whole triangle. Workgroups take 64-row blocks in the
 // order they start (a ticket counter), so a workgroup only ever waits on
-// blocks owned by workgroups that started before it. Each of its 4 waves
-// accumulates op(T)(block, j)·x_j over every fourth earlier block j as soon as
-// that block's solution is published; wave 0 then solves the 64×64 diagonal
-// block with lanes over rows (readlane broadcasts x_k) and publishes x_b.
-// Published solutions go through a separate buffer written and read with
-// device-coherent atomic accesses, and the ready flag is set only after those
-// stores have completed. The triangle is read once: the solve is bound by HBM
-// bandwidth and by the chain of n/64 diagonal solves.
+// blocks owned by workgroups that started before it.
+//
+// Wave 0 holds the block's rows of the diagonal block and the right-hand
+// side in registers; waves 1..3 take every third earlier block: each loads
+// its 64×64 tile of op(T) first (through LDS for the transposed case, so the
+// loads stay coalesced), then waits for that block's solution and subtracts
+// the product. After one barrier wave 0 solves the diagonal block by
+// substitution (reciprocals of the diagonal formed up front, readlane
+// broadcasts, the 64 steps unrolled so the row's entries stay in fixed
+// registers) and publishes x. Published solutions are 64-bit words holding
+// the launch's epoch in the upper half and one half of a value in the lower
+// half, written and polled with device-coherent atomic accesses: a reader
+// needs no flag, no fence and no reset. The triangle is read once, so the
+// solve is bound by HBM bandwidth and by the chain of n/64 diagonal solves.
 // ---------------------------------------------------------------------------
 struct TrsvArgs {
     long long n;
     int nrhs, nb;
     long long ldt, ldb;
-    int trans, lower_eff, unit, epoch;
+    int trans, lower_eff, unit;
+    unsigned int epoch;
     unsigned long long *ticket;
     unsigned long long ticket_base;
-    int *ready;
-    double *xbuf;   // [n][8]
+    unsigned long long *xw;   // [n][8][2] epoch-tagged halves of x
     DevStatus *st;
 };
 
@@ -293,118 +299,128 @@ __device__ __forceinline__ double rl_readlane(double x, int l) {
 
 template <typename TT, typename TB, int NR>
 __global__ __launch_bounds__(256) void trsv_k(const TT *__restrict__ T, TB *__restrict__ B, TrsvArgs a) {
-    __shared__ double xs[4][64][NR];
-    __shared__ double red[4][64][NR];
-    __shared__ double Dsh[64][65];
+    __shared__ double tile[3][64][65];
+    __shared__ double xs[3][64][NR];
+    __shared__ double red[3][64][NR];
     __shared__ int bsh;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) bsh = (int)(atomicAdd(a.ticket, 1ull) - a.ticket_base);
     __syncthreads();
     const int b = bsh, nb = a.nb;
-    // the diagonal block, loaded by the whole workgroup before any wait
-    {
-        const bool fwd0 = a.lower_eff != 0;
-        const long long rb = (long long)(fwd0 ? b : nb - 1 - b) * 64;
-        const int nr0 = (int)min(64LL, a.n - rb);
-        double v[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int idx = tid + 256 * u, ii = idx % 64, kk = idx / 64;
-            const bool in = ii < nr0 && kk < nr0;
-            const long long r = rb + (in ? ii : 0), cc = rb + (in ? kk : 0);
-            v[u] = (double)(a.trans ? T[cc + r * a.ldt] : T[r + cc * a.ldt]);
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int idx = tid + 256 * u, ii = idx % 64, kk = idx / 64;
-            const bool in = ii < nr0 && kk < nr0;
-            Dsh[ii][kk] = in ? v[u] : (ii == kk ? 1.0 : 0.0);
-        }
-    }
     const bool fwd = a.lower_eff != 0;
-    const long long n = a.n;
+    const long long n = a.n, ldt = a.ldt;
     const int pb = fwd ? b : nb - 1 - b;
     const long long r0 = (long long)pb * 64;
     const int nrow = (int)min(64LL, n - r0);
     const int nq = a.nrhs;
-    const long long ri = r0 + lane;
-    // element (r, c) of op(T)
-    auto M = [&](long long r, long long c) -> double {
-        return (double)(a.trans ? T[c + r * a.ldt] : T[r + c * a.ldt]);
-    };
+    const long long ri = r0 + min(lane, nrow - 1);   // clamped row of this lane
+    const unsigned long long ET = (unsigned long long)a.epoch << 32;
 
-    double acc[NR];
+    double d[64];      // wave 0: row `lane` of the diagonal block (strictly off-diagonal part)
+    double r[NR];      // wave 0: right-hand side, then solution
+    double rinv = 1.0;
+    if (wave == 0) {
 #pragma unroll
-    for (int q = 0; q < NR; ++q) acc[q] = 0.0;
-    for (int jj = wave; jj < b; jj += 4) {
-        const int pj = fwd ? jj : nb - 1 - jj;
-        const long long c0 = (long long)pj * 64;
-        const int ncol = (int)min(64LL, n - c0);
-        if (lane == 0) {
-            unsigned int spins = 0;
-            while (__hip_atomic_load(&a.ready[jj], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != a.epoch) {
-                if (++spins > (1u << 24)) { atomicExch(&a.st->error, 2); break; }
+        for (int k = 0; k < 64; ++k) {
+            const long long c = r0 + min(k, nrow - 1);
+            d[k] = (double)(a.trans ? T[c + ri * ldt] : T[ri + c * ldt]);
+        }
+        const double dd = (double)T[ri + ri * ldt];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) r[q] = (double)B[ri + min(q, nq - 1) * a.ldb];
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int k = 0; k < 64; ++k) {
+            const bool off = fwd ? (k < lane) : (k > lane);
+            d[k] = (lane < nrow && k < nrow && off) ? d[k] : 0.0;
+        }
+        rinv = (a.unit || lane >= nrow) ? 1.0 : 1.0 / dd;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) r[q] = (lane < nrow && q < nq) ? r[q] : 0.0;
+    } else {
+        const int w = wave - 1;
+        double acc[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc[q] = 0.0;
+        for (int jj = w; jj < b; jj += 3) {
+            const int pj = fwd ? jj : nb - 1 - jj;
+            const long long c0 = (long long)pj * 64;
+            const int ncol = (int)min(64LL, n - c0);
+            // the tile first: its loads overlap the wait for the block's solution
+            double mk[64];
+            if (!a.trans) {
+#pragma unroll
+                for (int k = 0; k < 64; ++k) mk[k] = (double)T[ri + (c0 + min(k, ncol - 1)) * ldt];
+            } else {
+                // op(T)(r, c) = T[c + r*ldt]: lanes over c read contiguously
+                const long long cl = c0 + min(lane, ncol - 1);
+#pragma unroll
+                for (int rr = 0; rr < 64; ++rr) tile[w][rr][lane] = (double)T[cl + (r0 + min(rr, nrow - 1)) * ldt];
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int k = 0; k < 64; ++k) mk[k] = tile[w][lane][k];
             }
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (lane < ncol) {
+            if (lane < ncol) {
+                unsigned long long *src = a.xw + (size_t)(c0 + lane) * 16;
 #pragma unroll
-            for (int q = 0; q < NR; ++q)
-                xs[wave][lane][q] = q < nq ? __hip_atomic_load(&a.xbuf[(c0 + lane) * 8 + q], __ATOMIC_RELAXED,
-                                                               __HIP_MEMORY_SCOPE_AGENT)
-                                           : 0.0;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (lane < nrow) {
-            // 16 matrix loads in flight at a time
-            for (int k0 = 0; k0 < ncol; k0 += 16) {
-                double mk[16];
-#pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const double v = M(ri, c0 + min(k0 + u, ncol - 1));   // clamped, unconditional
-                    mk[u] = (k0 + u < ncol) ? v : 0.0;
+                for (int q = 0; q < NR; ++q) {
+                    if (q < nq) {
+                        unsigned long long lo, hi;
+                        unsigned spins = 0;
+                        while (true) {
+                            lo = __hip_atomic_load(&src[2 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            hi = __hip_atomic_load(&src[2 * q + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            if ((lo >> 32) == a.epoch && (hi >> 32) == a.epoch) break;
+                            if (++spins > (1u << 22)) { atomicExch(&a.st->error, 2); break; }
+                        }
+                        xs[w][lane][q] = __hiloint2double((int)(unsigned)hi, (int)(unsigned)lo);
+                    } else {
+                        xs[w][lane][q] = 0.0;
+                    }
                 }
-#pragma unroll
-                for (int u = 0; u < 16; ++u)
-#pragma unroll
-                    for (int q = 0; q < NR; ++q) acc[q] -= mk[u] * xs[wave][min(k0 + u, 63)][q];
             }
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int q = 0; q < NR; ++q) red[wave][lane][q] = acc[q];
+            for (int k = 0; k < 64; ++k) {
+                if (k < ncol) {
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) acc[q] -= mk[k] * xs[w][k][q];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+#pragma unroll
+        for (int q = 0; q < NR; ++q) red[w][lane][q] = acc[q];
+    }
     __syncthreads();
     if (wave == 0) {
-        double r[NR];
 #pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            double v = (lane < nrow && q < nq) ? (double)B[ri + q * a.ldb] : 0.0;
-            r[q] = v + red[0][lane][q] + red[1][lane][q] + red[2][lane][q] + red[3][lane][q];
-        }
-        for (int s = 0; s < nrow; ++s) {
-            const int k = fwd ? s : nrow - 1 - s;   // uniform
-            const double dkk = Dsh[lane][k];
+        for (int q = 0; q < NR; ++q)
+            r[q] = lane < nrow ? r[q] + ((red[0][lane][q] + red[1][lane][q]) + red[2][lane][q]) : 0.0;
+        // substitution: x_k = r_k / t_kk, then r_i -= t_ik·x_k on the rows after k
+#pragma unroll
+        for (int s = 0; s < 64; ++s) {
+            const int k = fwd ? s : 63 - s;
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
-                const double xk = rl_readlane(a.unit ? r[q] : r[q] / dkk, k);
-                if (lane == k) r[q] = xk;
-                else if (fwd ? lane > k : lane < k) r[q] -= dkk * xk;
+                const double xk = rl_readlane(r[q] * rinv, k);
+                r[q] = (lane == k) ? xk : r[q] - d[k] * xk;
             }
         }
         if (lane < nrow) {
+            unsigned long long *dst = a.xw + (size_t)(r0 + lane) * 16;
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
                 if (q < nq) {
                     B[ri + q * a.ldb] = (TB)r[q];
-                    __hip_atomic_store(&a.xbuf[ri * 8 + q], r[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&dst[2 * q], ET | (unsigned)__double2loint(r[q]), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&dst[2 * q + 1], ET | (unsigned)__double2hiint(r[q]), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
         }
-        __builtin_amdgcn_s_waitcnt(0);   // published values have completed
     }
-    __syncthreads();
-    if (tid == 0) __hip_atomic_store(&a.ready[b], a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename TT, typename TB>
@@ -412,18 +428,17 @@ static void trsv(Ctx &c, bool lower_eff, bool trans, bool unit, long long m, lon
                  long long ldt, TB *B, long long ldb) {
     const int nb = (int)((m + 63) / 64);
     TrsvWork wk = trsv_work(c, m, nb, (int)((nrhs + 7) / 8));
-    if (!wk.xbuf) return;
+    if (!wk.xw) return;
     trace_begin(c, PK_TRSM_LEAF);
     for (long long q0 = 0; q0 < nrhs; q0 += 8) {
         TrsvArgs a{};
         a.n = m; a.nrhs = (int)min(8LL, nrhs - q0); a.nb = nb;
         a.ldt = ldt; a.ldb = ldb;
         a.trans = trans; a.lower_eff = lower_eff; a.unit = unit;
-        a.epoch = wk.epoch + (int)(q0 / 8);
+        a.epoch = wk.epoch + (unsigned)(q0 / 8);
         a.ticket = wk.ticket;
         a.ticket_base = wk.ticket_base + (unsigned long long)nb * (unsigned long long)(q0 / 8);
-        a.ready = wk.ready;
-        a.xbuf = wk.xbuf;
+        a.xw = wk.xw;
         a.st = c.dstat;
         if (a.nrhs == 1)
             hipLaunchKernelGGL((trsv_k<TT, TB, 1>), dim3(nb), dim3(256), 0, c.stream, T, B + q0 * ldb, a);
