@@ -421,31 +421,43 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
                 // every record whole in one round trip: the headers, one word per
                 // thread, and the windows, a wave per record and a lane per word
                 const int nwin = NC * nw;
-                unsigned long long hv, wv[kPanelStageG / 4];
-                const int hg = min(tid >> 2, G - 1);
+                constexpr int NQ = kPanelStageG / 4;
+                const unsigned long long *hp =
+                    &a.rec[((size_t)j * kRecSlots + min(tid >> 2, G - 1)) * kRecWords + (tid & 3)];
+                const unsigned long long *wpq[NQ];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    wpq[q] = &a.rec[((size_t)j * kRecSlots + min(wave + 4 * q, G - 1)) * kRecWords + 4 +
+                                    min(lane, nwin - 1)];
+                auto issue = [&](unsigned long long &h, unsigned long long *wv) {
+                    h = subw(hp);
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) wv[q] = subw(wpq[q]);
+                };
+                auto fresh = [&](unsigned long long h, const unsigned long long *wv) {
+                    bool ok = tid >= 4 * G || (unsigned)(h >> 32) == E;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        ok = ok && (wave + 4 * q >= G || lane >= nwin || (unsigned)(wv[q] >> 32) == E);
+                    return ok;
+                };
+                auto stage_in = [&](unsigned long long h, const unsigned long long *wv) {
+                    if (tid < 4 * G) stage[(tid >> 2) * kRecWords + (tid & 3)] = (unsigned)h;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        if (wave + 4 * q < G && lane < nwin) stage[(wave + 4 * q) * kRecWords + 4 + lane] = (unsigned)wv[q];
+                };
+                unsigned long long ha, wa[NQ];
                 unsigned spins = 0;
                 while (true) {
-                    hv = subw(&a.rec[((size_t)j * kRecSlots + hg) * kRecWords + (tid & 3)]);
-#pragma unroll
-                    for (int q = 0; q < kPanelStageG / 4; ++q) {
-                        const int rg = min(wave + 4 * q, G - 1);
-                        wv[q] = subw(&a.rec[((size_t)j * kRecSlots + rg) * kRecWords + 4 + min(lane, nwin - 1)]);
-                    }
-                    bool ok = tid >= 4 * G || (unsigned)(hv >> 32) == E;
-#pragma unroll
-                    for (int q = 0; q < kPanelStageG / 4; ++q)
-                        ok = ok && (wave + 4 * q >= G || lane >= nwin || (unsigned)(wv[q] >> 32) == E);
-                    if (ok) break;
+                    issue(ha, wa);
+                    if (fresh(ha, wa)) { stage_in(ha, wa); break; }
                     if (++spins > kPanelSpin) { atomicExch(&st->error, 1); abort_s = 1; break; }
                     if ((spins & 1023u) == 0 && __hip_atomic_load(&st->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                         abort_s = 1;
                         break;
                     }
                 }
-                if (tid < 4 * G) stage[(tid >> 2) * kRecWords + (tid & 3)] = (unsigned)hv;
-#pragma unroll
-                for (int q = 0; q < kPanelStageG / 4; ++q)
-                    if (wave + 4 * q < G && lane < nwin) stage[(wave + 4 * q) * kRecWords + 4 + lane] = (unsigned)wv[q];
                 __syncthreads();
                 if (abort_s) return;
                 // every wave reduces the headers itself (lanes over workgroups)
@@ -595,18 +607,14 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
         // x[q] <- x[q+1] - l·u[q+1] over the whole window: entries past the
         // live columns are never read, and a branch here would make the
         // compiler copy the window between registers at every step
+        {
+            T uc[W - 1];
 #pragma unroll
-        for (int c = 0; c < W / 8; ++c) {
-            T uc[8];
-#pragma unroll
-            for (int v = 0; v < 8; ++v) uc[v] = (8 * c + v + 1 < W) ? u[8 * c + v + 1] : T(0);
+            for (int q = 0; q < W - 1; ++q) uc[q] = u[q + 1];
 #pragma unroll
             for (int k = 0; k < 2; ++k)
 #pragma unroll
-                for (int v = 0; v < 8; ++v) {
-                    const int q = 8 * c + v;
-                    if (q < W - 1) x[k][q] = x[k][q + 1] - lk[k] * uc[v];
-                }
+                for (int q = 0; q < W - 1; ++q) x[k][q] = x[k][q + 1] - lk[k] * uc[q];
         }
     }
     __syncthreads();

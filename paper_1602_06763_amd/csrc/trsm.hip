@@ -7,8 +7,7 @@
 // which the integer test matrices rely on.
 //
 // Leaf: solve N·x = b for many vectors b, N a t×t triangle (t <= 64) held in
-// LDS. Each lane owns one right-hand-side vector and keeps it in registers.
-// Element (i, j) of N is T[i*ti + j*tj]; element e of vector r is
+// LDS. Element (i, j) of N is T[i*ti + j*tj]; element e of vector r is
 // B[e*se + r*sr]. Left-side solves use se = 1 (columns of B), right-side
 // solves use sr = 1 (rows of B) with N = op(T)ᵀ.
 #include "common.hpp"
@@ -16,84 +15,6 @@
 #include <type_traits>
 
 namespace rl {
-
-// Column-oriented substitution: once x_j is known every later x_i receives
-// its -N(i,j)·x_j at once, so a lane's 2016 multiply-adds are independent
-// within each column and pipeline instead of forming one long chain. N is
-// held transposed in LDS (NT[j][i] = N(i,j)) so a column is contiguous and the
-// broadcast reads pair up. FULL: t == 64 without per-element guards (kept for
-// reference; it spills, so the launcher always takes the guarded form).
-template <typename TT, typename TB, typename TW, bool FULL, bool LOWER>
-__global__ __launch_bounds__(256) void trsm_leaf_k(int unit, int t, const TT *__restrict__ T,
-                                                   long long ti, long long tj, long long nvec,
-                                                   TB *__restrict__ B, long long se, long long sr,
-                                                   const int *abort) {
-    if (abort && *abort) return;
-    __shared__ __attribute__((aligned(16))) TW NT[64][64 + 2];
-    const int tid = threadIdx.x;
-    // 16 unconditional loads per thread (t*t <= 4096), clamped to the triangle's corner
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const int idx = tid + 256 * u;
-        const int i = idx % 64, j = idx / 64;
-        const bool in = i < t && j < t && (LOWER ? (j <= i) : (j >= i));
-        const TW v = (TW)T[(in ? i : 0) * ti + (in ? j : 0) * tj];
-        NT[j][i] = in ? v : TW(0);
-    }
-    __syncthreads();
-    const long long r = (long long)blockIdx.x * 256 + tid;
-    if (r >= nvec) return;
-    TB *b = B + r * sr;
-    TW x[64];
-    // 8 loads at a time: 64 precomputed 64-bit addresses would not fit beside x
-#pragma unroll
-    for (int e = 0; e < 64; ++e) {
-        const TW v = (TW)b[(e < t ? e : t - 1) * se];   // clamped, unconditional
-        x[e] = (FULL || e < t) ? v : TW(0);
-        if ((e & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-    }
-
-    if (LOWER) {
-#pragma unroll
-        for (int j = 0; j < 64; ++j) {
-            if (FULL || j < t) {
-                const TW xj = unit ? x[j] : x[j] / NT[j][j];
-                x[j] = xj;
-#pragma unroll
-                for (int i = j + 1; i < 64; ++i) {
-                    if (FULL || i < t) x[i] -= NT[j][i] * xj;
-                    // bound how many LDS reads are in flight (x already holds 64 registers)
-                    if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    } else {
-#pragma unroll
-        for (int j = 63; j >= 0; --j) {
-            if (FULL || j < t) {
-                const TW xj = unit ? x[j] : x[j] / NT[j][j];
-                x[j] = xj;
-#pragma unroll
-                for (int i = 0; i < j; ++i) {
-                    x[i] -= NT[j][i] * xj;
-                    if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    }
-    // an opaque copy of the row pointer: the store addresses are recomputed
-    // instead of keeping all 64 load addresses live across the solve
-    TB *bs = b;
-    asm volatile("" : "+v"(bs));
-#pragma unroll
-    for (int e = 0; e < 64; ++e) {
-        if (FULL || e < t) bs[e * se] = (TB)x[e];
-        if ((e & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-    }
-}
-
 
 // ---------------------------------------------------------------------------
 // Matrix-core leaf: a workgroup solves N·x = b for 64 vectors (16 per wave),
