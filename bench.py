@@ -16,6 +16,9 @@ dpotrf + dgetrf pass right after them records HIP events around every kernel
 launch (library tracing) for the kernel-family breakdown and the roofline of
 the dominant kernel, the FP64 matrix-core GEMM on 128×128 tiles.
 
+``target_size`` additionally times one dpotrf and one dgetrf at n = 32768
+(``--target-n``), the size at which the FP64 matrix-core fraction is targeted.
+
 Prints ONE JSON line. ``--gpus N`` with N > 1 exits: this build runs on one GPU.
 ``--copy-calib MB`` only runs a plain device copy of that size 20 times (the
 reference point for the HBM byte counters) and prints nothing else.
@@ -52,6 +55,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-n", type=int, default=5120)
     p.add_argument("--copy-calib", type=float, default=0.0, help="MB; run only a plain device copy")
+    p.add_argument("--target-n", type=int, default=32768,
+                   help="also time one dpotrf + dgetrf at this size (0: skip)")
     return p.parse_args()
 
 
@@ -99,6 +104,41 @@ def cpu_baseline(n: int):
     return {"value": flops / (t2 - t0) / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"oracle dpotrf + dgetrf, one n={n} instance each (same generators), "
                       f"{t1 - t0:.1f} s + {t2 - t1:.1f} s"}
+
+
+def target_size(n: int, stream):
+    """One dpotrf and one dgetrf at the target size (same generators), each
+    after an untimed warm-up call on the same input."""
+    import torch
+
+    import gen
+    import paper_1602_06763_amd as rl
+
+    res = {"n": n}
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    for name, make, flops in (("potrf", lambda: gen.spd_bbt_torch(n, seed=0, device="cuda"), n ** 3 / 3.0),
+                              ("getrf", lambda: gen.general_uniform_torch(n, n, seed=1, device="cuda"),
+                               2.0 * n ** 3 / 3.0)):
+        A0 = make()
+        A = A0.clone()
+        piv = torch.zeros(n, dtype=torch.int32, device="cuda")
+        call = (lambda: rl.potrf(A, "L")) if name == "potrf" else (lambda: rl.getrf(A, piv))
+        assert call() == 0
+        A.copy_(A0)
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        info = call()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        assert info == 0
+        ms = e0.elapsed_time(e1)
+        res[name + "_ms"] = round(ms, 3)
+        res[name + "_tflops"] = round(flops / (ms * 1e-3) / 1e12, 3)
+        res[name + "_frac_of_fp64_peak"] = round(flops / (ms * 1e-3) / 1e12 / PEAK_FP64, 4)
+        del A0, A
+        torch.cuda.empty_cache()
+    return res
 
 
 def copy_calibration(mb: float):
@@ -280,6 +320,8 @@ def main():
             "general": {"ms": round(mg, 3), "fp64_solve_ms": round(fg, 3), "speedup": round(fg / mg, 3),
                         "info": last["mixed_ge"][0], "iter": last["mixed_ge"][1], "berr": last["mixed_ge"][2]},
         }
+    if args.target_n > 0:
+        out["target_size"] = target_size(args.target_n, stream)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
     print(json.dumps(out))

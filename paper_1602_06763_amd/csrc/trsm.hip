@@ -21,13 +21,48 @@ namespace rl {
 // triangle t <= 64 in LDS, blocked by 16: block I of x is
 //     x_I = N_II⁻¹ (b_I - Σ_{J before I} N_IJ·x_J),
 // the sum on the matrix cores (16×16×4 steps, vectors as columns), the 16×16
-// diagonal solve by substitution on 16 lanes (one vector each). The
-// reciprocals of the diagonal are formed once while the triangle is staged,
-// and rows beyond t are padded with the identity, so the substitution is
-// straight-line code with one multiply and one FMA on its dependency chain
+// diagonal solve by substitution with four lanes per vector. The reciprocals
+// of the diagonal are formed once after the triangle is staged, and rows
+// beyond t are padded with the identity, so the substitution is straight-line
+// code with a multiply, a quad broadcast and an FMA on its dependency chain
 // per step. Each wave works on its own 16 vectors, so waves never wait for
 // each other after the triangle is staged.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double lane_bcast(double x, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_bcast(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// The value of lane S of each group of four lanes, in all four (DPP quad_perm).
+template <int S>
+__device__ __forceinline__ float quad_bcast(float x) {
+    constexpr int ctrl = S | (S << 2) | (S << 4) | (S << 6);
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xF, 0xF, false));
+}
+template <int S>
+__device__ __forceinline__ double quad_bcast(double x) {
+    constexpr int ctrl = S | (S << 2) | (S << 4) | (S << 6);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// quad_bcast with the source lane chosen at run time; fully unrolled callers
+// pass a constant, so the switch folds away.
+template <typename T>
+__device__ __forceinline__ T quad_bcast_sel(T x, int s) {
+    switch (s & 3) {
+    case 0: return quad_bcast<0>(x);
+    case 1: return quad_bcast<1>(x);
+    case 2: return quad_bcast<2>(x);
+    default: return quad_bcast<3>(x);
+    }
+}
+
 template <typename TW>
 struct LeafMfma;
 template <>
@@ -56,52 +91,46 @@ __global__ __launch_bounds__(256) void trsm_leaf_mfma_k(int unit, int t, const T
     typedef typename Op::acc_t acc_t;
     __shared__ TW Nsh[64][65];
     __shared__ TW Xsh[4][64][17];
-    __shared__ TW rdiag[64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // stage the triangle (zero outside it and beyond t): 16 unconditional loads per thread
+    const long long v0 = (long long)blockIdx.x * 64 + wave * 16;   // this wave's 16 vectors
+    TW (*X)[17] = Xsh[wave];
+    // the triangle (16 elements per thread) and the vectors (16 per thread),
+    // all loads in flight before any is used
     {
-        TW v[16];
+        TW tv[16], bv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
+            tv[u] = (TW)T[min(i, t - 1) * ti + min(j, t - 1) * tj];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int e, q;
+            if (se == 1) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
+            else { q = lane & 15; e = (lane >> 4) + 4 * u; }
+            bv[u] = (TB)B[min(e, t - 1) * se + min(v0 + q, nvec - 1) * sr];
+        }
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
             const bool in = i < t && j < t && (LOWER ? (j <= i) : (j >= i));
-            v[u] = (TW)T[(in ? i : 0) * ti + (in ? j : 0) * tj];
-            v[u] = in ? v[u] : TW(0);
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
-            Nsh[i][j] = (i == j && i >= t) ? TW(1) : v[u];
-        }
-        if (tid < 64) {
-            // T(i, i) straight from memory: the staged copy is written by another thread
-            const TW dii = (TW)T[min(tid, max(t - 1, 0)) * (ti + tj)];
-            rdiag[tid] = (unit || tid >= t) ? TW(1) : TW(1) / dii;
-        }
-    }
-    // this wave's 16 vectors, element-major in LDS
-    const long long v0 = (long long)blockIdx.x * 64 + wave * 16;
-    TW (*X)[17] = Xsh[wave];
-    {
-        TW v[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            int e, q;
-            if (se == 1) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
-            else { q = lane & 15; e = (lane >> 4) + 4 * u; }
-            const bool in = e < t && v0 + q < nvec;
-            v[u] = (TW)B[in ? e * se + (v0 + q) * sr : 0];
-            v[u] = in ? v[u] : TW(0);
+            // zero outside the triangle; the identity beyond t
+            Nsh[i][j] = in ? tv[u] : ((i == j && i >= t) ? TW(1) : TW(0));
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             int e, q;
             if (se == 1) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
             else { q = lane & 15; e = (lane >> 4) + 4 * u; }
-            X[e][q] = v[u];
+            X[e][q] = (e < t && v0 + q < nvec) ? (TW)bv[u] : TW(0);
         }
     }
     __syncthreads();
+    // reciprocal of diagonal element `lane`, formed in every wave off the
+    // substitution's dependency chain (read back with readlane)
+    TW rdl = (unit || lane >= t) ? TW(1) : TW(1) / Nsh[lane][lane];
+    asm volatile("" : "+v"(rdl));
 
     const int nblk = (t + 15) / 16;
     for (int s = 0; s < nblk; ++s) {
@@ -121,30 +150,49 @@ __global__ __launch_bounds__(256) void trsm_leaf_mfma_k(int unit, int t, const T
             for (int v = 0; v < 4; ++v) X[16 * I + Op::row(lane, v)][lane & 15] -= acc[v];
             __builtin_amdgcn_wave_barrier();
         }
-        // diagonal 16×16 block: lanes 0..15 each finish one vector
-        if (lane < 16) {
-            TW x[16];
+        // diagonal 16×16 block: four lanes per vector (lane = 4·vector + r,
+        // rows 4r..4r+3 of the block), so all 64 lanes work and each step's
+        // x_j reaches the vector's other lanes by a quad broadcast; the
+        // block's reciprocals come from readlane in uniform control flow and
+        // the next column's entries are read ahead of the current updates
+        TW rds[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) x[i] = X[16 * I + i][lane];
-            if (LOWER) {
+        for (int j = 0; j < 16; ++j) rds[j] = lane_bcast(rdl, 16 * I + j);
+        {
+            const int v = lane >> 2, r4 = lane & 3;
+            TW x[4], nc[4], nn[4];
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    const TW xj = x[j] * rdiag[16 * I + j];
-                    x[j] = xj;
+            for (int t4 = 0; t4 < 4; ++t4) x[t4] = X[16 * I + 4 * r4 + t4][v];
 #pragma unroll
-                    for (int i = j + 1; i < 16; ++i) x[i] -= Nsh[16 * I + i][16 * I + j] * xj;
+            for (int t4 = 0; t4 < 4; ++t4) nc[t4] = Nsh[16 * I + 4 * r4 + t4][16 * I + (LOWER ? 0 : 15)];
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) {
+                const int j = LOWER ? s2 : 15 - s2, jb = j >> 2, jj = j & 3;
+                if (s2 + 1 < 16) {
+#pragma unroll
+                    for (int t4 = 0; t4 < 4; ++t4) nn[t4] = Nsh[16 * I + 4 * r4 + t4][16 * I + (LOWER ? j + 1 : j - 1)];
                 }
-            } else {
+                // the column read one step ago is complete here; the empty asm
+                // also keeps the compiler from turning the selects below into
+                // branches around the loads
 #pragma unroll
-                for (int j = 15; j >= 0; --j) {
-                    const TW xj = x[j] * rdiag[16 * I + j];
-                    x[j] = xj;
+                for (int t4 = 0; t4 < 4; ++t4) asm volatile("" : "+v"(nc[t4]));
+                const TW xs = x[jj] * rds[j];
+                const TW xb = quad_bcast_sel(xs, jb);
 #pragma unroll
-                    for (int i = 0; i < j; ++i) x[i] -= Nsh[16 * I + i][16 * I + j] * xj;
+                for (int t4 = 0; t4 < 4; ++t4) {
+                    const TW f = x[t4] - nc[t4] * xb;
+                    // rows after j in the order of the solve take the update,
+                    // row j takes its solved value, the others stay
+                    const bool after = LOWER ? (t4 > jj ? r4 >= jb : r4 > jb) : (t4 < jj ? r4 <= jb : r4 < jb);
+                    const TW keep = (t4 == jj && r4 == jb) ? xs : x[t4];
+                    x[t4] = after ? f : keep;
                 }
+#pragma unroll
+                for (int t4 = 0; t4 < 4; ++t4) nc[t4] = nn[t4];
             }
 #pragma unroll
-            for (int i = 0; i < 16; ++i) X[16 * I + i][lane] = x[i];
+            for (int t4 = 0; t4 < 4; ++t4) X[16 * I + 4 * r4 + t4][v] = x[t4];
         }
         __builtin_amdgcn_wave_barrier();
     }
