@@ -24,6 +24,9 @@ these stand in for them):
 * ``diag_dominant`` column diagonally dominant (no row interchange at all).
 * ``conditioned``   A = Q·diag(σ)·Qᵀ (SPD) or U·diag(σ)·Vᵀ (general) with a
                     prescribed 2-norm condition number κ, and b = A·x₀.
+* ``triangular``    a row-diagonally-dominant triangle (triangular inverse and
+                    product inputs); ``unit_bidiagonal`` a triangle with a
+                    closed-form inverse.
 """
 from __future__ import annotations
 
@@ -170,6 +173,35 @@ def diag_dominant(n: int, seed: int = 0) -> np.ndarray:
     sgn = np.where(rng(seed + 1).integers(0, 2, size=n) == 0, 1.0, -1.0)
     a[np.diag_indices(n)] = sgn * (colsum + n)
     return _fortran(a)
+
+
+def triangular(n: int, uplo: str = "L", diag: str = "N", seed: int = 0) -> np.ndarray:
+    """A well-conditioned triangle (the input of the triangular inverse and
+    product). Strict ``uplo`` part uniform[-1, 1]; diag = 'N': diagonal
+    n·(1 + uniform[0, 1]), so every row is diagonally dominant with a margin;
+    diag = 'U': the strict part is divided by n and the diagonal is 1. The
+    strict other triangle is 0.
+
+    Draw order: an (n, n) block of uniform[-1, 1], then n uniform[0, 1].
+    """
+    g = rng(seed)
+    off = g.uniform(-1.0, 1.0, size=(n, n))
+    d = g.uniform(0.0, 1.0, size=n)
+    t = np.tril(off, -1) if uplo in ("L", "l") else np.triu(off, 1)
+    if diag in ("U", "u"):
+        t = t / max(n, 1)
+        t[np.diag_indices(n)] = 1.0
+    else:
+        t[np.diag_indices(n)] = n * (1.0 + d)
+    return _fortran(t)
+
+
+def unit_bidiagonal(n: int, s: float = 1.0) -> np.ndarray:
+    """L = I + s·(ones on the first subdiagonal): inv(L)_ij = (-s)^(i-j) for
+    i >= j, and A = L·Lᵀ is the tridiagonal matrix with diagonal (1, 1+s², …)
+    and off-diagonal s, whose Cholesky factor is L itself."""
+    lo = np.eye(n) + s * np.eye(n, k=-1)
+    return _fortran(lo)
 
 
 def tridiag_121(n: int) -> np.ndarray:

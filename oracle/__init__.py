@@ -20,6 +20,15 @@ Parity status of each function (what pins it is in ``tests/test_oracle_pins.py``
                        exactness of the binary64 scaling, RNE rounding.
 * ``backward_error``   pinned: exact solutions give 0, hand-checked 2×2 case,
                        scaling invariance.
+* ``trtri``            pinned: closed-form inverse of integer bidiagonal
+                       triangles (exact), exact rational inverses by brute
+                       force (n <= 6), reciprocals of a diagonal, unit
+                       diagonal never read, zero pivot reported before any
+                       write, residual bound, upper/lower transposition.
+* ``lauum``            pinned: exact integer products against integer matrix
+                       multiplication, identity, strict other triangle untouched.
+* ``potri``            pinned: exact integer inverse of A = L·Lᵀ with unit
+                       bidiagonal L, residual bound ‖A·X − I‖.
 """
 from __future__ import annotations
 
@@ -72,6 +81,10 @@ def lib() -> ctypes.CDLL:
         L.oracle_scale_ge_f32.restype = None
         L.oracle_backward_error.argtypes = [c_char, c_int, c_int, dp, c_int, dp, c_int, dp, c_int, dp]
         L.oracle_backward_error.restype = c_double
+        L.oracle_dtrtri.argtypes = [c_char, c_char, c_int, dp, c_int]
+        L.oracle_dtrtri.restype = c_int
+        L.oracle_dlauum.argtypes = [c_char, c_int, dp, c_int]
+        L.oracle_dlauum.restype = None
         L.oracle_set_threads.argtypes = [c_int]
         L.oracle_set_threads.restype = None
         L.oracle_get_threads.argtypes = []
@@ -141,6 +154,36 @@ def getrs(lu, ipiv, b, trans: str = "N"):
     ip = np.ascontiguousarray(ipiv, dtype=np.int32)
     lib().oracle_dgetrs(trans.encode(), n, nrhs, _dp(lu), max(n, 1), _ip(ip), _dp(b), max(n, 1))
     return b
+
+
+def trtri(a, uplo: str = "L", diag: str = "N"):
+    """Inverse of the ``uplo`` triangle of a copy of ``a`` in place; returns (array, info)."""
+    a = _f64(a)
+    n = a.shape[0]
+    info = lib().oracle_dtrtri(uplo.encode(), diag.encode(), n, _dp(a), max(n, 1))
+    return a, int(info)
+
+
+def lauum(a, uplo: str = "L"):
+    """Lᵀ·L (uplo 'L') or U·Uᵀ (uplo 'U') of the triangle of a copy of ``a``, in that triangle."""
+    a = _f64(a)
+    n = a.shape[0]
+    lib().oracle_dlauum(uplo.encode(), n, _dp(a), max(n, 1))
+    return a
+
+
+def potri(a, uplo: str = "L"):
+    """Inverse of an SPD matrix through its Cholesky factor: potrf, then trtri
+    of the factor, then lauum (the LAPACK composition xpotri, which the paper
+    names as the user of xtrtri and xlauum in Sec. 5). Returns (array, info);
+    only the ``uplo`` triangle of the result is meaningful."""
+    f, info = potrf(a, uplo)
+    if info:
+        return f, info
+    f, info = trtri(f, uplo, "N")
+    if info:
+        return f, info
+    return lauum(f, uplo), 0
 
 
 def scale_spd_f32(a, uplo: str = "L"):

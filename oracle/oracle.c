@@ -250,6 +250,96 @@ void oracle_dgetrs(char trans, int n, int nrhs, const double *A, int lda, const 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Triangular inverse and triangular product (the SPD-inverse follow-on).     */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Inverse of a triangular matrix (xtrtri, Sec. 5; the worked example of
+ * Sec. 3, Fig. blocked_alg and Fig. recursive_alg: A := A^-1 in place).
+ * Definition used: column j of X = T^-1 solves T·x = e_j, by substitution in
+ * the order of the triangle (forward for lower, backward for upper):
+ *   lower: x_i = (delta_ij - sum_{k=j}^{i-1} t_ik·x_k) / t_ii,  i = j..n-1,
+ *   upper: x_i = (delta_ij - sum_{k=i+1}^{j} t_ik·x_k) / t_ii,  i = j..0,
+ * each sum taken in increasing k, one rounded multiply and one rounded
+ * subtract per term. diag = 'U': t_ii is taken as 1 and never read, and the
+ * diagonal of A is left as it is. As in LAPACK, a non-unit triangle with an
+ * exact zero on the diagonal is reported (info = first such index, 1-based)
+ * before anything is written. The strict other triangle is never touched.
+ */
+int oracle_dtrtri(char uplo, char diag, int n, double *A, int lda)
+{
+    const int lower = is_lower(uplo);
+    const int unit = (diag == 'U' || diag == 'u');
+    if (!unit)
+        for (int i = 0; i < n; ++i)
+            if (AT(A, lda, i, i) == 0.0) return i + 1;
+    double *X = (double *)calloc((size_t)n * (size_t)(n > 0 ? n : 1), sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j) {
+        double *x = X + (size_t)j * (size_t)n;
+        if (lower) {
+            for (int i = j; i < n; ++i) {
+                double s = (i == j) ? 1.0 : 0.0;
+                for (int k = j; k < i; ++k) s = s - AT(A, lda, i, k) * x[k];
+                x[i] = unit ? s : s / AT(A, lda, i, i);
+            }
+        } else {
+            for (int i = j; i >= 0; --i) {
+                double s = (i == j) ? 1.0 : 0.0;
+                for (int k = i + 1; k <= j; ++k) s = s - AT(A, lda, i, k) * x[k];
+                x[i] = unit ? s : s / AT(A, lda, i, i);
+            }
+        }
+    }
+    for (int j = 0; j < n; ++j) {
+        const double *x = X + (size_t)j * (size_t)n;
+        if (lower) {
+            for (int i = unit ? j + 1 : j; i < n; ++i) AT(A, lda, i, j) = x[i];
+        } else {
+            for (int i = 0; i <= (unit ? j - 1 : j); ++i) AT(A, lda, i, j) = x[i];
+        }
+    }
+    free(X);
+    return 0;
+}
+
+/*
+ * Product of a triangular matrix with its transpose (xlauum, Sec. 5):
+ *   uplo = 'L': A := Lᵀ·L,  (Lᵀ·L)_ij = sum_{k=max(i,j)}^{n-1} l_ki·l_kj,
+ *   uplo = 'U': A := U·Uᵀ,  (U·Uᵀ)_ij = sum_{k=max(i,j)}^{n-1} u_ik·u_jk,
+ * each sum in increasing k; the result's own triangle (the one the factor
+ * came in) is written, the strict other triangle is never touched.
+ */
+void oracle_dlauum(char uplo, int n, double *A, int lda)
+{
+    const int lower = is_lower(uplo);
+    double *C = (double *)calloc((size_t)n * (size_t)(n > 0 ? n : 1), sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j) {
+        if (lower) {
+            for (int i = j; i < n; ++i) {
+                double s = 0.0;
+                for (int k = i; k < n; ++k) s = s + AT(A, lda, k, i) * AT(A, lda, k, j);
+                C[(size_t)j * n + i] = s;
+            }
+        } else {
+            for (int i = 0; i <= j; ++i) {
+                double s = 0.0;
+                for (int k = j; k < n; ++k) s = s + AT(A, lda, i, k) * AT(A, lda, j, k);
+                C[(size_t)j * n + i] = s;
+            }
+        }
+    }
+    for (int j = 0; j < n; ++j) {
+        if (lower)
+            for (int i = j; i < n; ++i) AT(A, lda, i, j) = C[(size_t)j * n + i];
+        else
+            for (int i = 0; i <= j; ++i) AT(A, lda, i, j) = C[(size_t)j * n + i];
+    }
+    free(C);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Mixed-precision preprocessing and the FP64 backward error.                */
 /* ------------------------------------------------------------------------ */
 

@@ -117,3 +117,20 @@ def lu_partial_pivoting(a, min_gap: float = 1e-6):
     for (i, k), v in Lf.items():
         L[pos[i], k] = float(v)
     return ipiv, L, U
+
+
+def inverse(a) -> list[list[Fraction]]:
+    """A⁻¹ by the adjugate: (A⁻¹)_ij = (-1)^(i+j)·det(A without row j and
+    column i) / det(A), every determinant by cofactor expansion."""
+    F = to_fractions(a)
+    n = len(F)
+    full = tuple(range(n))
+    d = det(F, full, full)
+    out = [[Fraction(0)] * n for _ in range(n)]
+    for i in range(n):
+        for j in range(n):
+            rows = tuple(r for r in full if r != j)
+            cols = tuple(c for c in full if c != i)
+            minor = det(F, rows, cols) if n > 1 else Fraction(1)
+            out[i][j] = (-1) ** (i + j) * minor / d
+    return out

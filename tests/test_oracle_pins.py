@@ -330,3 +330,130 @@ def test_backward_error_definition(orc):
     e1 = orc.backward_error(s, y, bb, "L")[0]
     e2 = orc.backward_error(4.0 * s, y, 4.0 * bb, "N")[0]
     assert e1 == pytest.approx(e2, rel=1e-12)
+
+
+# ------------------------------------------------ triangular inverse / product
+
+@pytest.mark.parametrize("n,s", [(1, 2.0), (9, 2.0), (40, 2.0), (300, 1.0), (120, -1.0)])
+@pytest.mark.parametrize("uplo", ["L", "U"])
+def test_trtri_bidiagonal_closed_form(orc, n, s, uplo):
+    lo = gen.unit_bidiagonal(n, s)
+    t = lo if uplo == "L" else lo.T.copy(order="F")
+    x, info = orc.trtri(t, uplo, "N")
+    assert info == 0
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    closed = np.where(i >= j, (-s) ** np.maximum(i - j, 0), 0.0)
+    if uplo == "U":
+        closed = closed.T
+    tri = np.tril if uplo == "L" else np.triu
+    assert np.array_equal(tri(x), closed)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (4, 2), (6, 3)])
+@pytest.mark.parametrize("uplo", ["L", "U"])
+def test_trtri_bruteforce_adjugate(orc, n, seed, uplo):
+    g = np.random.default_rng(seed)
+    t = g.integers(-5, 6, size=(n, n)).astype(np.float64)
+    t = np.tril(t) if uplo == "L" else np.triu(t)
+    t[np.diag_indices(n)] = g.choice([-3.0, -2.0, 1.0, 3.0, 5.0, 7.0], size=n)
+    x, info = orc.trtri(t, uplo, "N")
+    assert info == 0
+    inv = exact.inverse(t)
+    ref = np.array([[float(v) for v in row] for row in inv])
+    tri = np.tril if uplo == "L" else np.triu
+    # each entry is within a few rounding errors of the exact rational value
+    scale = np.abs(ref).max()
+    assert np.abs(tri(x) - ref).max() <= 64 * n * U64 * scale
+    # the other triangle of the exact inverse is zero
+    assert np.all(ref[np.triu_indices(n, 1) if uplo == "L" else np.tril_indices(n, -1)] == 0)
+
+
+def test_trtri_diagonal_and_unit(orc):
+    d = np.array([4.0, -2.0, 3.0, 0.1, 7.0])
+    x, info = orc.trtri(np.diag(d), "L", "N")
+    assert info == 0 and np.array_equal(np.diag(x), 1.0 / d)
+    # unit diagonal: the stored diagonal is never read and never written
+    t = gen.triangular(30, "L", "U", seed=4)
+    t[np.diag_indices(30)] = np.nan
+    x, info = orc.trtri(t, "L", "U")
+    assert info == 0 and np.isnan(np.diag(x)).all()
+    ref = t.copy()
+    ref[np.diag_indices(30)] = 1.0
+    xx = np.tril(x, -1) + np.eye(30)
+    assert np.abs(ref @ xx - np.eye(30)).max() <= 30 * 30 * U64
+
+
+@pytest.mark.parametrize("uplo", ["L", "U"])
+def test_trtri_zero_pivot_reported_before_writing(orc, uplo):
+    t = gen.triangular(12, uplo, "N", seed=5)
+    t[7, 7] = 0.0
+    t[9, 9] = 0.0
+    x, info = orc.trtri(t, uplo, "N")
+    assert info == 8
+    assert np.array_equal(x, t)
+    # the same matrix with diag = 'U' has nothing to report
+    _, info = orc.trtri(t, uplo, "U")
+    assert info == 0
+
+
+@pytest.mark.parametrize("n", [50, 333])
+def test_trtri_residual_and_transpose(orc, n):
+    t = gen.triangular(n, "L", "N", seed=n)
+    x, info = orc.trtri(t, "L", "N")
+    assert info == 0
+    xl = np.tril(x)
+    res = np.abs(t @ xl - np.eye(n)).max()
+    assert res <= 4 * n * U64 * np.abs(t).max() * np.abs(xl).max() * n
+    # T upper = Lᵀ: its inverse is the transpose (up to summation order)
+    xu, info = orc.trtri(t.T.copy(order="F"), "U", "N")
+    assert info == 0
+    assert np.abs(np.triu(xu) - xl.T).max() <= 8 * n * U64 * np.abs(xl).max()
+    # strict other triangle untouched
+    assert np.all(np.triu(x, 1) == 0)
+
+
+@pytest.mark.parametrize("n", [1, 5, 64, 129])
+@pytest.mark.parametrize("uplo", ["L", "U"])
+def test_lauum_exact_integers(orc, n, uplo):
+    g = np.random.default_rng(n)
+    t = g.integers(-3, 4, size=(n, n))
+    t = np.tril(t) if uplo == "L" else np.triu(t)
+    ref = t.T @ t if uplo == "L" else t @ t.T          # integer matrix product, exact
+    s = t.astype(np.float64, order="F")
+    other = np.triu_indices(n, 1) if uplo == "L" else np.tril_indices(n, -1)
+    s[other] = np.nan
+    out = orc.lauum(s, uplo)
+    tri = np.tril if uplo == "L" else np.triu
+    assert np.array_equal(tri(np.nan_to_num(out, nan=0.0)), tri(ref).astype(np.float64))
+    assert np.isnan(out[other]).all()
+
+
+def test_lauum_identity_and_diagonal(orc):
+    assert np.array_equal(orc.lauum(np.eye(7), "L"), np.eye(7))
+    d = np.diag([3.0, -2.0, 0.5])
+    assert np.array_equal(orc.lauum(d, "U"), d * d)
+
+
+@pytest.mark.parametrize("n", [1, 7, 200])
+@pytest.mark.parametrize("uplo", ["L", "U"])
+def test_potri_exact_bidiagonal(orc, n, uplo):
+    lo = gen.unit_bidiagonal(n, 1.0)
+    a = lo @ lo.T                        # tridiagonal, integers
+    x, info = orc.potri(a, uplo)
+    assert info == 0
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    closed = ((-1.0) ** (i + j)) * (n - np.maximum(i, j))   # inv(L)ᵀ·inv(L)
+    tri = np.tril if uplo == "L" else np.triu
+    assert np.array_equal(tri(x), tri(closed))
+    assert np.abs(a @ closed - np.eye(n)).max() == 0
+
+
+def test_potri_residual(orc):
+    n = 160
+    a = gen.spd_bbt(n, seed=9)
+    x, info = orc.potri(a, "L")
+    assert info == 0
+    full = np.tril(x) + np.tril(x, -1).T
+    assert np.abs(a @ full - np.eye(n)).max() <= 10 * n * U64 * np.abs(a).sum(1).max() * np.abs(full).sum(1).max()
+    _, info = orc.potri(-a, "L")
+    assert info == 1
