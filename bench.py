@@ -17,7 +17,9 @@ launch (library tracing) for the kernel-family breakdown and the roofline of
 the dominant kernel, the FP64 matrix-core GEMM on 128×128 tiles.
 
 ``target_size`` additionally times one dpotrf and one dgetrf at n = 32768
-(``--target-n``), the size at which the FP64 matrix-core fraction is targeted.
+(``--target-n``), the size at which the FP64 matrix-core fraction is targeted;
+``spd_inverse`` times dpotri (dtrtri + dlauum of the Cholesky factor) at
+n = 8192 (``--inv-n``).
 
 Prints ONE JSON line. ``--gpus N`` with N > 1 exits: this build runs on one GPU.
 ``--copy-calib MB`` only runs a plain device copy of that size 20 times (the
@@ -57,6 +59,8 @@ def parse():
     p.add_argument("--copy-calib", type=float, default=0.0, help="MB; run only a plain device copy")
     p.add_argument("--target-n", type=int, default=32768,
                    help="also time one dpotrf + dgetrf at this size (0: skip)")
+    p.add_argument("--inv-n", type=int, default=8192,
+                   help="also time the SPD inverse (dtrtri + dlauum of a dpotrf factor) at this size (0: skip)")
     return p.parse_args()
 
 
@@ -139,6 +143,62 @@ def target_size(n: int, stream):
         del A0, A
         torch.cuda.empty_cache()
     return res
+
+
+def spd_inverse(n: int, stream, reps: int = 3):
+    """dpotri = dtrtri + dlauum on the Cholesky factor of the n×n SPD input
+    (same generator as dpotrf), the factor restored from a pristine copy before
+    each untimed-then-timed call; median of ``reps`` timed calls, each with
+    the normwise residual ‖A·X − I‖_max of the last one."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1602_06763_amd as rl
+
+    A0 = gen.spd_bbt_torch(n, seed=0, device="cuda")
+    F0 = A0.clone()
+    assert rl.potrf(F0, "L") == 0
+    A = F0.clone()
+    ts, tt, tl = [], [], []
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    for r in range(reps + 1):
+        A.copy_(F0)
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        info = rl.potri(A, "L")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        assert info == 0
+        if r > 0:
+            ts.append(e0.elapsed_time(e1))
+    # the two halves separately, for the breakdown
+    for r in range(reps):
+        A.copy_(F0)
+        torch.cuda.synchronize()
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record(stream)
+        assert rl.trtri(A, "L", "N") == 0
+        e1.record(stream)
+        assert rl.lauum(A, "L") == 0
+        e2.record(stream)
+        torch.cuda.synchronize()
+        tt.append(e0.elapsed_time(e1))
+        tl.append(e1.elapsed_time(e2))
+    X = torch.tril(A) + torch.tril(A, -1).T
+    R = A0 @ X
+    R.diagonal().sub_(1.0)
+    resid = float(R.abs().max()) / (float(A0.abs().sum(1).max()) * float(X.abs().sum(1).max()))
+    ms, mt, ml = float(np.median(ts)), float(np.median(tt)), float(np.median(tl))
+    fl = 2.0 * n ** 3 / 3.0
+    del A0, F0, A, X, R
+    torch.cuda.empty_cache()
+    return {"n": n, "potri_ms": round(ms, 3), "potri_tflops": round(fl / (ms * 1e-3) / 1e12, 3),
+            "potri_frac_of_fp64_peak": round(fl / (ms * 1e-3) / 1e12 / PEAK_FP64, 4),
+            "trtri_ms": round(mt, 3), "lauum_ms": round(ml, 3),
+            "residual_AX_minus_I_rel": resid,
+            "flops": "n^3/3 (dtrtri) + n^3/3 (dlauum)"}
 
 
 def copy_calibration(mb: float):
@@ -322,6 +382,8 @@ def main():
         }
     if args.target_n > 0:
         out["target_size"] = target_size(args.target_n, stream)
+    if args.inv_n > 0:
+        out["spd_inverse"] = spd_inverse(args.inv_n, stream)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
     print(json.dumps(out))

@@ -150,6 +150,51 @@ void relapack_dsyrk(char uplo, char trans, int n, int k, double alpha, const dou
 void relapack_dtrsm(char side, char uplo, char transa, char diag, int m, int n, const double *A,
                     int lda, double *B, int ldb, int *info);
 
+/*
+ * Triangular matrix product (xtrmm; step (2) of the recursive inversion in
+ * Sec. 3, Fig. recursive_alg): B := alpha·op(A)·B (side 'L', A m×m) or
+ * B := alpha·B·op(A) (side 'R', A n×n); A triangular (uplo), unit diagonal if
+ * diag = 'U' (then its diagonal is not read). B: m×n, overwritten. Recursive
+ * down to a 64×64 matrix-core leaf.
+ * Errors: side -1, uplo -2, transa -3, diag -4, m -5, n -6, lda -9, ldb -11.
+ */
+void relapack_dtrmm(char side, char uplo, char transa, char diag, int m, int n, double alpha,
+                    const double *A, int lda, double *B, int ldb, int *info);
+
+/* ---- SPD inverse (xtrtri, xlauum; Sec. 5) ------------------------------ */
+
+/*
+ * Inverse of a triangular matrix in place (xtrtri, Sec. 5; the recursive
+ * algorithm of Sec. 3, Fig. recursive_alg: invert A_TL, A_BL := A_BL·A_TL,
+ * A_BL := −A_BR⁻¹·A_BL, invert A_BR; unblocked below 64). uplo selects the
+ * triangle; diag = 'U': unit diagonal, not read and not written. The strict
+ * other triangle is neither read nor written.
+ * info = i > 0: A(i,i) is exactly zero (diag = 'N'); this is checked before
+ * anything is written, and A is then left unchanged.
+ * Errors: uplo -1, diag -2, n -3, lda -5.
+ */
+void relapack_dtrtri(char uplo, char diag, int n, double *A, int lda, int *info);
+
+/*
+ * Product of a triangle with its own transpose in place (xlauum, Sec. 5):
+ * uplo = 'L': the lower triangle of A becomes that of Lᵀ·L; uplo = 'U': the
+ * upper triangle becomes that of U·Uᵀ. Recursive: lauum(A_TL), A_TL +=
+ * A_BLᵀ·A_BL (matrix-core SYRK), A_BL := A_BRᵀ·A_BL (trmm), lauum(A_BR).
+ * The strict other triangle is neither read nor written.
+ * Errors: uplo -1, n -2, lda -4.
+ */
+void relapack_dlauum(char uplo, int n, double *A, int lda, int *info);
+
+/*
+ * Inverse of an SPD matrix from its Cholesky factor (xpotri, the user of
+ * xtrtri and xlauum named in Sec. 5): on entry the factor from
+ * relapack_dpotrf(uplo, ...); on exit the uplo triangle of A⁻¹ = L⁻ᵀ·L⁻¹
+ * (uplo 'L') or U⁻¹·U⁻ᵀ (uplo 'U'), i.e. dtrtri(uplo, 'N') then dlauum(uplo).
+ * info = i > 0: the factor's (i,i) entry is exactly zero; A is unchanged.
+ * Errors: uplo -1, n -2, lda -4.
+ */
+void relapack_dpotri(char uplo, int n, double *A, int lda, int *info);
+
 /* ---- pieces of the mixed-precision path -------------------------------- */
 
 /*
@@ -189,14 +234,16 @@ void relapack_trace_enable(int on);
  * algorithmic flops, algorithmic bytes}; families: 1 potf2, 2 trsm leaf,
  * 3 gemm on 64×64 tiles and 12 gemm on 128×128 tiles, 4 syrk (FP64 matrix
  * cores), 5 getf2 panel, 6 laswp, 7 convert, 8 residual, 10 gemm and 11 syrk
- * with FP32/FP16/BF16 operands. Single-kernel families are timed by the
+ * with FP32/FP16/BF16 operands, 13 triangular-inverse leaf, 14 trmm leaf,
+ * 15 lauum leaf. Single-kernel families are timed by the
  * kernel's own start/end timestamps, the others by events around them.
  * Synchronizes the stream and clears the records. Returns cap, or -1 on a
  * HIP error. */
 int relapack_trace_collect(double *out, int cap);
 
 /* The kernel-call sequence of one factorization without launching anything
- * (no GPU needed): routine "potrf_L", "potrf_U" or "getrf"; leaf > 0
+ * (no GPU needed): routine "potrf_L", "potrf_U", "getrf", "trtri_L",
+ * "trtri_U", "lauum_L" or "lauum_U"; leaf > 0
  * overrides every crossover size. Writes up to cap records of 5 int64
  * {kind, depth, m, n, k} to rec; returns the total number of calls. */
 long long relapack_plan(const char *routine, long long m, long long n, int leaf, long long *rec,

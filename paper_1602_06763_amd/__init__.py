@@ -43,6 +43,11 @@ _SIGS = {
                         _ip], None),
     "relapack_dtrsm": ([_c_char, _c_char, _c_char, _c_char, _c_int, _c_int, _vp, _c_int, _vp, _c_int, _ip],
                        None),
+    "relapack_dtrmm": ([_c_char, _c_char, _c_char, _c_char, _c_int, _c_int, _c_double, _vp, _c_int, _vp,
+                        _c_int, _ip], None),
+    "relapack_dtrtri": ([_c_char, _c_char, _c_int, _vp, _c_int, _ip], None),
+    "relapack_dlauum": ([_c_char, _c_int, _vp, _c_int, _ip], None),
+    "relapack_dpotri": ([_c_char, _c_int, _vp, _c_int, _ip], None),
     "relapack_scale_spd_f32": ([_c_char, _c_int, _vp, _c_int, _vp, _vp, _c_int, _ip], None),
     "relapack_scale_ge_f32": ([_c_int, _vp, _c_int, _vp, _vp, _vp, _c_int, _ip], None),
     "relapack_spotrf_lp": ([_c_char, _c_int, _vp, _c_int, _c_int, _ip], None),
@@ -54,7 +59,8 @@ _SIGS = {
 }
 
 TRACE_FAMILIES = {1: "potf2", 2: "trsm_leaf", 3: "gemm", 4: "syrk", 5: "getf2_panel", 6: "laswp",
-                  7: "convert", 8: "residual", 10: "gemm_lowprec", 11: "syrk_lowprec", 12: "gemm128"}
+                  7: "convert", 8: "residual", 10: "gemm_lowprec", 11: "syrk_lowprec", 12: "gemm128",
+                  13: "trti2", 14: "trmm_leaf", 15: "lauu2"}
 
 PREC = {"fp32": 32, "32": 32, 32: 32, "fp16": 16, "16": 16, 16: 16, "bf16": ord("b"), "b": ord("b")}
 
@@ -195,6 +201,35 @@ def trsm(side, uplo, transa, diag, m, n, A, lda, B, ldb) -> int:
     info = ctypes.c_int(0)
     lib().relapack_dtrsm(_b(side), _b(uplo), _b(transa), _b(diag), m, n, _ptr(A), lda, _ptr(B), ldb,
                          ctypes.byref(info))
+    return info.value
+
+
+def trmm(side, uplo, transa, diag, m, n, alpha, A, lda, B, ldb) -> int:
+    info = ctypes.c_int(0)
+    lib().relapack_dtrmm(_b(side), _b(uplo), _b(transa), _b(diag), m, n, alpha, _ptr(A), lda, _ptr(B), ldb,
+                         ctypes.byref(info))
+    return info.value
+
+
+def trtri(A, uplo: str = "L", diag: str = "N", n: int | None = None, lda: int | None = None) -> int:
+    n = A.shape[0] if n is None else n
+    info = ctypes.c_int(0)
+    lib().relapack_dtrtri(_b(uplo), _b(diag), n, _ptr(A), _ld(A, n) if lda is None else lda,
+                          ctypes.byref(info))
+    return info.value
+
+
+def lauum(A, uplo: str = "L", n: int | None = None, lda: int | None = None) -> int:
+    n = A.shape[0] if n is None else n
+    info = ctypes.c_int(0)
+    lib().relapack_dlauum(_b(uplo), n, _ptr(A), _ld(A, n) if lda is None else lda, ctypes.byref(info))
+    return info.value
+
+
+def potri(A, uplo: str = "L", n: int | None = None, lda: int | None = None) -> int:
+    n = A.shape[0] if n is None else n
+    info = ctypes.c_int(0)
+    lib().relapack_dpotri(_b(uplo), n, _ptr(A), _ld(A, n) if lda is None else lda, ctypes.byref(info))
     return info.value
 
 

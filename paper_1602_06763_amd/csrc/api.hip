@@ -551,6 +551,72 @@ void relapack_sgetrf_lp(int m, int n, float *A, int lda, int *ipiv, int prec, in
     *info = call_end(c);
 }
 
+// ---- triangular product, inverse, SPD inverse ------------------------------
+
+void relapack_dtrmm(char side, char uplo, char transa, char diag, int m, int n, double alpha,
+                    const double *A, int lda, double *B, int ldb, int *info) {
+    if (!info) return;
+    if (!is(side, 'L') && !is(side, 'R')) { *info = -1; return; }
+    if (!is(uplo, 'L') && !is(uplo, 'U')) { *info = -2; return; }
+    if (!is(transa, 'N') && !is(transa, 'T') && !is(transa, 'C')) { *info = -3; return; }
+    if (!is(diag, 'N') && !is(diag, 'U')) { *info = -4; return; }
+    if (m < 0) { *info = -5; return; }
+    if (n < 0) { *info = -6; return; }
+    const int nrowa = is(side, 'L') ? m : n;
+    if (lda < (nrowa > 1 ? nrowa : 1)) { *info = -9; return; }
+    if (ldb < (m > 1 ? m : 1)) { *info = -11; return; }
+    *info = 0;
+    if (m == 0 || n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    trmm(c, side, uplo, transa, diag, m, n, alpha, A, lda, B, ldb);
+    *info = call_end(c);
+}
+
+void relapack_dtrtri(char uplo, char diag, int n, double *A, int lda, int *info) {
+    if (!info) return;
+    if (!is(uplo, 'L') && !is(uplo, 'U')) { *info = -1; return; }
+    if (!is(diag, 'N') && !is(diag, 'U')) { *info = -2; return; }
+    if (n < 0) { *info = -3; return; }
+    if (lda < (n > 1 ? n : 1)) { *info = -5; return; }
+    *info = 0;
+    if (n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, true)) { *info = call_end(c); return; }
+    if (is(diag, 'N')) diag_zero(c, n, A, lda);
+    trtri_rec(c, is(uplo, 'L') ? 'L' : 'U', is(diag, 'U') ? 'U' : 'N', n, A, lda);
+    *info = call_end(c);
+}
+
+void relapack_dlauum(char uplo, int n, double *A, int lda, int *info) {
+    if (!info) return;
+    if (!is(uplo, 'L') && !is(uplo, 'U')) { *info = -1; return; }
+    if (n < 0) { *info = -2; return; }
+    if (lda < (n > 1 ? n : 1)) { *info = -4; return; }
+    *info = 0;
+    if (n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    lauum_rec(c, is(uplo, 'L') ? 'L' : 'U', n, A, lda);
+    *info = call_end(c);
+}
+
+void relapack_dpotri(char uplo, int n, double *A, int lda, int *info) {
+    if (!info) return;
+    if (!is(uplo, 'L') && !is(uplo, 'U')) { *info = -1; return; }
+    if (n < 0) { *info = -2; return; }
+    if (lda < (n > 1 ? n : 1)) { *info = -4; return; }
+    *info = 0;
+    if (n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, true)) { *info = call_end(c); return; }
+    const char u = is(uplo, 'L') ? 'L' : 'U';
+    diag_zero(c, n, A, lda);
+    trtri_rec(c, u, 'N', n, A, lda);
+    lauum_rec(c, u, n, A, lda);
+    *info = call_end(c);
+}
+
 // ---- tracing ----------------------------------------------------------------
 
 void relapack_trace_enable(int on) {
@@ -582,7 +648,8 @@ int relapack_trace_collect(double *out, int cap) {
 
 // ---- plan mode: the call sequence of one factorization, without launching ---
 
-// routine: "potrf_L", "potrf_U" or "getrf". Writes up to cap records of
+// routine: "potrf_L", "potrf_U", "getrf", "trtri_L", "trtri_U", "lauum_L" or
+// "lauum_U". Writes up to cap records of
 // {kind, level, m, n, k} (5 int64 each) into rec; returns the total count.
 long long relapack_plan(const char *routine, long long m, long long n, int leaf, long long *rec,
                         long long cap) {
@@ -598,6 +665,8 @@ long long relapack_plan(const char *routine, long long m, long long n, int leaf,
     if (r == "potrf_L") potrf_rec<double>(c, Mfma::F64, 'L', n, nullptr, n, 0);
     else if (r == "potrf_U") potrf_rec<double>(c, Mfma::F64, 'U', n, nullptr, n, 0);
     else if (r == "getrf") getrf_top<double>(c, Mfma::F64, m, n, nullptr, m, nullptr);
+    else if (r == "trtri_L" || r == "trtri_U") trtri_rec(c, r[6], 'N', n, nullptr, n);
+    else if (r == "lauum_L" || r == "lauum_U") lauum_rec(c, r[6], n, nullptr, n);
     else { c = saved; return -1; }
     c = saved;
     for (long long i = 0; i < (long long)out.size() && i < cap; ++i) {

@@ -52,7 +52,8 @@ struct PlanRec {
 enum PlanKind : int {
     PK_POTF2 = 1, PK_TRSM_LEAF = 2, PK_GEMM = 3, PK_SYRK = 4, PK_GETF2 = 5, PK_LASWP = 6,
     PK_CONVERT = 7, PK_RESID = 8, PK_OTHER = 9, PK_GEMM_LP = 10, PK_SYRK_LP = 11,
-    PK_GEMM_BIG = 12   // FP64 GEMM launches on 128×128 tiles (traced separately from PK_GEMM)
+    PK_GEMM_BIG = 12,  // FP64 GEMM launches on 128×128 tiles (traced separately from PK_GEMM)
+    PK_TRTI2 = 13, PK_TRMM_LEAF = 14, PK_LAUU2 = 15
 };
 
 // Per-thread library state: stream, plan recording, tracing.
@@ -148,6 +149,16 @@ void laswp_leaf(Ctx &c, long long ncols_total, T *A, long long lda, long long k0
 template <typename T>
 void laswp_rows(Ctx &c, long long n, T *B, long long ldb, const int *ipiv, long long k1, long long k2,
                 bool reverse);
+
+// Triangular product, inverse and Lᵀ·L / U·Uᵀ (FP64): B := α·op(T)·B (side
+// 'L') or α·B·op(T) (side 'R'); the recursive xtrtri and xlauum; the first
+// zero on the diagonal into the call's info.
+void trmm(Ctx &c, char side, char uplo, char trans, char diag, long long m, long long n, double alpha,
+          const double *T, long long ldt, double *B, long long ldb);
+void trtri_rec(Ctx &c, char uplo, char diag, long long n, double *A, long long lda);
+void lauum_rec(Ctx &c, char uplo, long long n, double *A, long long lda);
+void diag_zero(Ctx &c, long long n, const double *A, long long lda);
+void trti2_leaf(Ctx &c, bool lower, bool unit, int t, double *A, long long lda);
 
 // Mixed precision helpers.
 void scale_spd_f32(Ctx &c, char uplo, long long n, const double *A, long long lda, double *d,

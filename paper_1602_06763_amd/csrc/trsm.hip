@@ -82,7 +82,11 @@ struct LeafMfma<float> {
     static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
-template <typename TT, typename TB, typename TW, bool LOWER>
+// INV = true: the right-hand sides are the columns of the identity (not read
+// from B) and only the triangle of the solution is written back, so a single
+// workgroup (nvec = t) writes N⁻¹ over N's own triangle in B = T; the whole
+// triangle is staged in LDS before the first store.
+template <typename TT, typename TB, typename TW, bool LOWER, bool INV = false>
 __global__ __launch_bounds__(256) void trsm_leaf_mfma_k(int unit, int t, const TT *__restrict__ T, long long ti,
                                                         long long tj, long long nvec, TB *__restrict__ B,
                                                         long long se, long long sr, const int *abort) {
@@ -108,7 +112,7 @@ __global__ __launch_bounds__(256) void trsm_leaf_mfma_k(int unit, int t, const T
             int e, q;
             if (se == 1) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
             else { q = lane & 15; e = (lane >> 4) + 4 * u; }
-            bv[u] = (TB)B[min(e, t - 1) * se + min(v0 + q, nvec - 1) * sr];
+            bv[u] = INV ? TB(e == v0 + q) : (TB)B[min(e, t - 1) * se + min(v0 + q, nvec - 1) * sr];
         }
         asm volatile("" ::: "memory");
 #pragma unroll
@@ -203,7 +207,9 @@ __global__ __launch_bounds__(256) void trsm_leaf_mfma_k(int unit, int t, const T
         int e, q;
         if (se == 1) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
         else { q = lane & 15; e = (lane >> 4) + 4 * u; }
-        if (e < t && v0 + q < nvec) B[e * se + (v0 + q) * sr] = (TB)X[e][q];
+        bool w = e < t && v0 + q < nvec;
+        if (INV) w = w && (LOWER ? (unit ? e > v0 + q : e >= v0 + q) : (unit ? e < v0 + q : e <= v0 + q));
+        if (w) B[e * se + (v0 + q) * sr] = (TB)X[e][q];
     }
 }
 
@@ -226,6 +232,23 @@ void trsm_leaf(Ctx &c, bool lower_eff, bool unit, int t, const TT *T, long long 
     (void)grid;
     RL_CHECK(hipGetLastError());
     trace_kernel_end(c, PK_TRSM_LEAF, (double)t * t * nvec, 8.0 * (t * t + 2.0 * t * nvec));
+}
+
+// Unblocked inverse of a t×t triangle (t <= 64) in place: the leaf solve
+// against the identity, one workgroup, only the triangle written back.
+void trti2_leaf(Ctx &c, bool lower, bool unit, int t, double *A, long long lda) {
+    if (plan_record(c, PK_TRTI2, t, t, t)) return;
+    if (t <= 0) return;
+    const int *abort = c.abort_on_info ? &c.dstat->info : nullptr;
+    trace_kernel_begin(c);
+    if (lower)
+        rl_launch(c, trsm_leaf_mfma_k<double, double, double, true, true>, dim3(1), dim3(256), 0, (int)unit, t,
+                  (const double *)A, 1LL, lda, (long long)t, A, 1LL, lda, abort);
+    else
+        rl_launch(c, trsm_leaf_mfma_k<double, double, double, false, true>, dim3(1), dim3(256), 0, (int)unit, t,
+                  (const double *)A, 1LL, lda, (long long)t, A, 1LL, lda, abort);
+    RL_CHECK(hipGetLastError());
+    trace_kernel_end(c, PK_TRTI2, (double)t * t * t / 3.0, 8.0 * t * t);
 }
 
 
