@@ -82,55 +82,15 @@ struct LeafMfma<float> {
     static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
-// INV = true: the right-hand sides are the columns of the identity (not read
-// from B) and only the triangle of the solution is written back, so a single
-// workgroup (nvec = t) writes N⁻¹ over N's own triangle in B = T; the whole
-// triangle is staged in LDS before the first store.
-template <typename TT, typename TB, typename TW, bool LOWER, bool INV = false>
-__global__ __launch_bounds__(256) void trsm_leaf_mfma_k(int unit, int t, const TT *__restrict__ T, long long ti,
-                                                        long long tj, long long nvec, TB *__restrict__ B,
-                                                        long long se, long long sr, const int *abort) {
-    if (abort && *abort) return;
+// One wave solves N·x = b for its 16 vectors, N the 64×64 triangle in Nsh
+// (rows and columns beyond t padded with the identity), x in the wave's X
+// (64 rows × 16 vectors): 16-row blocks in the order of the solve, each first
+// updated on the matrix cores with the blocks already solved, then finished
+// by substitution.
+template <typename TW, bool LOWER>
+__device__ __forceinline__ void solve64(TW (*Nsh)[65], TW (*X)[17], int t, int unit, int lane) {
     typedef LeafMfma<TW> Op;
     typedef typename Op::acc_t acc_t;
-    __shared__ TW Nsh[64][65];
-    __shared__ TW Xsh[4][64][17];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const long long v0 = (long long)blockIdx.x * 64 + wave * 16;   // this wave's 16 vectors
-    TW (*X)[17] = Xsh[wave];
-    // the triangle (16 elements per thread) and the vectors (16 per thread),
-    // all loads in flight before any is used
-    {
-        TW tv[16], bv[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
-            tv[u] = (TW)T[min(i, t - 1) * ti + min(j, t - 1) * tj];
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            int e, q;
-            if (se == 1) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
-            else { q = lane & 15; e = (lane >> 4) + 4 * u; }
-            bv[u] = INV ? TB(e == v0 + q) : (TB)B[min(e, t - 1) * se + min(v0 + q, nvec - 1) * sr];
-        }
-        asm volatile("" ::: "memory");
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
-            const bool in = i < t && j < t && (LOWER ? (j <= i) : (j >= i));
-            // zero outside the triangle; the identity beyond t
-            Nsh[i][j] = in ? tv[u] : ((i == j && i >= t) ? TW(1) : TW(0));
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            int e, q;
-            if (se == 1) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
-            else { q = lane & 15; e = (lane >> 4) + 4 * u; }
-            X[e][q] = (e < t && v0 + q < nvec) ? (TW)bv[u] : TW(0);
-        }
-    }
-    __syncthreads();
     // reciprocal of diagonal element `lane`, formed in every wave off the
     // substitution's dependency chain (read back with readlane)
     TW rdl = (unit || lane >= t) ? TW(1) : TW(1) / Nsh[lane][lane];
@@ -201,6 +161,59 @@ __global__ __launch_bounds__(256) void trsm_leaf_mfma_k(int unit, int t, const T
         __builtin_amdgcn_wave_barrier();
     }
 
+}
+
+// INV = true: the right-hand sides are the columns of the identity (not read
+// from B) and only the triangle of the solution is written back, so a single
+// workgroup (nvec = t) writes N⁻¹ over N's own triangle in B = T; the whole
+// triangle is staged in LDS before the first store.
+template <typename TT, typename TB, typename TW, bool LOWER, bool INV = false>
+__global__ __launch_bounds__(256) void trsm_leaf_mfma_k(int unit, int t, const TT *__restrict__ T, long long ti,
+                                                        long long tj, long long nvec, TB *__restrict__ B,
+                                                        long long se, long long sr, const int *abort) {
+    if (abort && *abort) return;
+    typedef LeafMfma<TW> Op;
+    typedef typename Op::acc_t acc_t;
+    __shared__ TW Nsh[64][65];
+    __shared__ TW Xsh[4][64][17];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long v0 = (long long)blockIdx.x * 64 + wave * 16;   // this wave's 16 vectors
+    TW (*X)[17] = Xsh[wave];
+    // the triangle (16 elements per thread) and the vectors (16 per thread),
+    // all loads in flight before any is used
+    {
+        TW tv[16], bv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
+            tv[u] = (TW)T[min(i, t - 1) * ti + min(j, t - 1) * tj];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int e, q;
+            if (se == 1) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
+            else { q = lane & 15; e = (lane >> 4) + 4 * u; }
+            bv[u] = INV ? TB(e == v0 + q) : (TB)B[min(e, t - 1) * se + min(v0 + q, nvec - 1) * sr];
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
+            const bool in = i < t && j < t && (LOWER ? (j <= i) : (j >= i));
+            // zero outside the triangle; the identity beyond t
+            Nsh[i][j] = in ? tv[u] : ((i == j && i >= t) ? TW(1) : TW(0));
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int e, q;
+            if (se == 1) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
+            else { q = lane & 15; e = (lane >> 4) + 4 * u; }
+            X[e][q] = (e < t && v0 + q < nvec) ? (TW)bv[u] : TW(0);
+        }
+    }
+    __syncthreads();
+    solve64<TW, LOWER>(Nsh, X, t, unit, lane);
+
     // write the solved vectors back
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -210,6 +223,104 @@ __global__ __launch_bounds__(256) void trsm_leaf_mfma_k(int unit, int t, const T
         bool w = e < t && v0 + q < nvec;
         if (INV) w = w && (LOWER ? (unit ? e > v0 + q : e >= v0 + q) : (unit ? e < v0 + q : e <= v0 + q));
         if (w) B[e * se + (v0 + q) * sr] = (TB)X[e][q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two-block leaf for 64 < t <= 128: the bottom level of the recursion (two
+// 64-leaves and the product between them) in one launch. The triangle is
+// N = [D0 0; O D1] (lower) or [D0 O; 0 D1] (upper); the workgroup solves
+// with the first diagonal block in the order of the solve, subtracts O times
+// that part from the other rows on the matrix cores, then restages LDS with
+// the second diagonal block (read into registers at the start) and solves
+// with it. 64 vectors per workgroup, 16 per wave, as in the one-block leaf.
+// ---------------------------------------------------------------------------
+template <typename TT, typename TB, typename TW, bool LOWER>
+__global__ __launch_bounds__(256) void trsm_leaf2_k(int unit, int t, const TT *__restrict__ T, long long ti,
+                                                    long long tj, long long nvec, TB *__restrict__ B,
+                                                    long long se, long long sr, const int *abort) {
+    if (abort && *abort) return;
+    typedef LeafMfma<TW> Op;
+    typedef typename Op::acc_t acc_t;
+    __shared__ TW Nsh[64][65];
+    __shared__ TW Osh[64][65];
+    __shared__ TW Xsh[4][128][17];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long v0 = (long long)blockIdx.x * 64 + wave * 16;
+    TW (*X)[17] = Xsh[wave];
+    const int t2 = t - 64;                                  // rows of the second block, 1..64
+    const int first = LOWER ? 0 : 1, second = 1 - first;    // blocks in the order of the solve
+    const int tf = first == 0 ? 64 : t2, ts = second == 0 ? 64 : t2;
+    TW dsec[16];
+    {
+        TW df[16], ov[16], bv[32];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
+            const int fi = min(64 * first + i, t - 1), fj = min(64 * first + j, t - 1);
+            const int si = min(64 * second + i, t - 1), sj = min(64 * second + j, t - 1);
+            const int oi = min(LOWER ? 64 + i : i, t - 1), oj = min(LOWER ? j : 64 + j, t - 1);
+            df[u] = (TW)T[fi * ti + fj * tj];
+            dsec[u] = (TW)T[si * ti + sj * tj];
+            ov[u] = (TW)T[oi * ti + oj * tj];
+        }
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            int e, q;
+            if (se == 1) { e = (lane & 15) + 16 * (u & 7); q = (lane >> 4) + 4 * (u >> 3); }
+            else { q = lane & 15; e = (lane >> 4) + 4 * u; }
+            bv[u] = (TW)B[min(e, t - 1) * se + min(v0 + q, nvec - 1) * sr];
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
+            const bool tri = LOWER ? (j <= i) : (j >= i);
+            Nsh[i][j] = (i < tf && j < tf && tri) ? df[u] : ((i == j && i >= tf) ? TW(1) : TW(0));
+            Osh[i][j] = (LOWER ? i < t2 : j < t2) ? ov[u] : TW(0);
+            dsec[u] = (i < ts && j < ts && tri) ? dsec[u] : ((i == j && i >= ts) ? TW(1) : TW(0));
+        }
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            int e, q;
+            if (se == 1) { e = (lane & 15) + 16 * (u & 7); q = (lane >> 4) + 4 * (u >> 3); }
+            else { q = lane & 15; e = (lane >> 4) + 4 * u; }
+            X[e][q] = (e < t && v0 + q < nvec) ? bv[u] : TW(0);
+        }
+    }
+    __syncthreads();
+    solve64<TW, LOWER>(Nsh, X + 64 * first, tf, unit, lane);
+    // the other rows: X_second -= O·X_first (four independent 16-row blocks)
+    {
+        acc_t acc[4];
+#pragma unroll
+        for (int I = 0; I < 4; ++I) acc[I] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int k4 = 0; k4 < 16; ++k4) {
+            const int k = 4 * k4 + (lane >> 4);
+            const TW b = X[64 * first + k][lane & 15];
+#pragma unroll
+            for (int I = 0; I < 4; ++I) acc[I] = Op::mma(Osh[16 * I + (lane & 15)][k], b, acc[I]);
+        }
+#pragma unroll
+        for (int I = 0; I < 4; ++I)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) X[64 * second + 16 * I + Op::row(lane, v)][lane & 15] -= acc[I][v];
+    }
+    __syncthreads();   // every wave is done with the first diagonal block
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
+        Nsh[i][j] = dsec[u];
+    }
+    __syncthreads();
+    solve64<TW, LOWER>(Nsh, X + 64 * second, ts, unit, lane);
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+        int e, q;
+        if (se == 1) { e = (lane & 15) + 16 * (u & 7); q = (lane >> 4) + 4 * (u >> 3); }
+        else { q = lane & 15; e = (lane >> 4) + 4 * u; }
+        if (e < t && v0 + q < nvec) B[e * se + (v0 + q) * sr] = (TB)X[e][q];
     }
 }
 
@@ -223,7 +334,14 @@ void trsm_leaf(Ctx &c, bool lower_eff, bool unit, int t, const TT *T, long long 
     trace_kernel_begin(c);
     typedef typename std::conditional<(sizeof(TB) == 8 || sizeof(TT) == 8), double, float>::type TW;
     const int grid64 = (int)((nvec + 63) / 64);
-    if (lower_eff)
+    if (t > 64) {
+        if (lower_eff)
+            rl_launch(c, trsm_leaf2_k<TT, TB, TW, true>, dim3(grid64), dim3(256), 0, (int)unit, t, T, ti, tj, nvec,
+                      B, se, sr, abort);
+        else
+            rl_launch(c, trsm_leaf2_k<TT, TB, TW, false>, dim3(grid64), dim3(256), 0, (int)unit, t, T, ti, tj, nvec,
+                      B, se, sr, abort);
+    } else if (lower_eff)
         rl_launch(c, trsm_leaf_mfma_k<TT, TB, TW, true>, dim3(grid64), dim3(256), 0, (int)unit, t, T, ti, tj, nvec, B,
                   se, sr, abort);
     else
@@ -458,13 +576,15 @@ void trsm(Ctx &c, Mfma mode, char side, char uplo, char trans, char diag, long l
     const bool unit = is(diag, 'U');
     const char opc = tr ? 'T' : 'N';
     const int leaf = c.plan && c.plan_leaf > 0 ? c.plan_leaf : kTrsmLeaf;
+    // the leaf kernels take up to two 64-blocks of the triangle
+    const int top = leaf == kTrsmLeaf ? 2 * kTrsmLeaf : leaf;
     if (is(side, 'L')) {
         // op(T)·X = B, X m×n, triangle m×m
-        if (!c.plan && n <= kTrsvMaxRhs && m > leaf) {
+        if (!c.plan && n <= kTrsvMaxRhs && m > top) {
             trsv<TT, TB>(c, lowerM, tr, unit, m, n, T, ldt, B, ldb);
             return;
         }
-        if (m <= leaf) {
+        if (m <= top) {
             trsm_leaf<TT, TB>(c, lowerM, unit, (int)m, T, tr ? ldt : 1, tr ? 1 : ldt, n, B, 1, ldb);
             return;
         }
@@ -483,7 +603,7 @@ void trsm(Ctx &c, Mfma mode, char side, char uplo, char trans, char diag, long l
         }
     } else {
         // X·op(T) = B, X m×n, triangle n×n. Row r of X solves op(T)ᵀ·xᵀ = bᵀ.
-        if (n <= leaf) {
+        if (n <= top) {
             // N = op(T)ᵀ: N(i,j) = op(T)(j,i) = tr ? T(i,j) : T(j,i)
             trsm_leaf<TT, TB>(c, !lowerM, unit, (int)n, T, tr ? 1 : ldt, tr ? ldt : 1, m, B, ldb, 1);
             return;
