@@ -33,6 +33,9 @@ constexpr int kRecWords = 72;       // 64-bit words per panel exchange record
 constexpr int kRecSlots = kPanelMaxWG + 1;   // per step: one per workgroup, one for row d
 constexpr int kTrsvMaxRhs = 32;     // left-side solves with at most this many right-hand sides
                                     // take the single-launch blocked solve
+constexpr int kLaswpBlock = 512;    // LU nodes wider than this apply interchanges in batches
+constexpr long long kLaswpBatchRows = 32768;   // batches need m <= this (a column's rows in registers)
+constexpr int kLaswpDepth = 12;     // batch-node depths with their own tracker inverses
 
 // Per-call status record shared by every kernel of one library call.
 struct DevStatus {
@@ -64,6 +67,12 @@ struct Ctx {
     DevStatus *hstat = nullptr;      // pinned host mirror
     int *rowsrc = nullptr;
     size_t rowsrc_elems = 0;
+    // LU with batched interchanges: row tracker (two buffers, current = pcur)
+    // and 2·kLaswpDepth + 1 inverse slots, each pv_m ints
+    bool lu_batch = false;
+    int *pv = nullptr;
+    long long pv_m = 0;
+    int pcur = 0;
     // plan mode: record instead of launch
     bool plan = false;
     std::vector<PlanRec> *plan_out = nullptr;
@@ -144,8 +153,16 @@ void trsm_leaf(Ctx &c, bool lower_eff, bool unit, int t, const TT *T, long long 
 template <typename T>
 void getf2_panel(Ctx &c, long long m, int w, T *A, long long lda, long long off, int *ipiv);
 template <typename T>
-void laswp_leaf(Ctx &c, long long ncols_total, T *A, long long lda, long long k0, int w, long long m,
-                const int *ipiv, long long skip_lo, long long skip_hi);
+void laswp_leaf(Ctx &c, T *A, long long lda, long long k0, int w, long long m, const int *ipiv, long long blk0,
+                long long blk1);
+// Row tracker of the batched interchanges: start (identity), inverse of the
+// current tracker over positions [r0, m) into inverse slot `slot`, and one
+// batch: columns [j0, j0+ncols), rows [r0, m), npiv pivots (for the records).
+void lu_track_begin(Ctx &c, long long m);
+int *lu_inverse(Ctx &c, int slot, long long r0, long long m);
+template <typename T>
+void laswp_batch(Ctx &c, T *A, long long lda, long long j0, long long ncols, long long r0, long long m,
+                 const int *inv, long long npiv);
 template <typename T>
 void laswp_rows(Ctx &c, long long n, T *B, long long ldb, const int *ipiv, long long k1, long long k2,
                 bool reverse);

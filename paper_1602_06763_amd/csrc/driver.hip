@@ -49,41 +49,71 @@ template void potrf_rec<float>(Ctx &, Mfma, char, long long, float *, long long,
 // ---------------------------------------------------------------------------
 // LU with partial pivoting on the columns [c0, c0+w) of an m×ncols matrix,
 // rows [c0, m).  getrf(left half); A12 := L11⁻¹·A12; A22 -= A21·A12;
-// getrf(right half).  Each leaf panel applies its interchanges to all other
-// columns at once (the row swaps of the left-hand and right-hand blocks that
-// the recursion performs after each half); every column receives exactly the
-// interchanges it would have received, in the same order, so the result is
-// the same.
+// getrf(right half).  Row interchanges reach every other column once, at the
+// latest before anything reads that column again:
+//  * nodes wider than kLaswpBlock follow the recursion's own order: after
+//    the left half is factored its pivots are applied to the right half's
+//    columns in one batch, and after the right half its pivots go to the left
+//    half's columns in one batch;
+//  * below that, each leaf panel applies its interchanges at once to the
+//    other columns of its block (the topmost node of at most kLaswpBlock
+//    columns, or the whole matrix when there are no batches).
+// Every column receives exactly the interchanges it would have received, in
+// the same order, so the result is the same as with the recursion's order
+// at every level.
 // ---------------------------------------------------------------------------
 template <typename T>
 static void getrf_rec(Ctx &c, Mfma mode, long long m, long long ncols, T *A, long long lda, int *ipiv,
-                      long long c0, long long w) {
+                      long long c0, long long w, long long blk0, long long blk1, int depth) {
     const int leaf = c.plan && c.plan_leaf > 0 ? c.plan_leaf : kLuLeaf;
     if (w <= leaf) {
         getf2_panel<T>(c, m, (int)w, A, lda, c0, ipiv);
-        laswp_leaf<T>(c, ncols, A, lda, c0, (int)w, m, ipiv, c0, c0 + w);
+        laswp_leaf<T>(c, A, lda, c0, (int)w, m, ipiv, blk0, blk1);
         return;
     }
     const long long w1 = split_size(w), w2 = w - w1;
+    const bool batch = c.lu_batch && w > kLaswpBlock && depth < kLaswpDepth;
+    // a child that is no batch node under a batch node starts its own block
+    const long long lb0 = batch ? c0 : blk0, lb1 = batch ? c0 + w1 : blk1;
+    const long long rb0 = batch ? c0 + w1 : blk0, rb1 = batch ? c0 + w : blk1;
+    const int *inv = batch ? lu_inverse(c, 2 * depth, c0, m) : nullptr;
     c.level++;
-    getrf_rec<T>(c, mode, m, ncols, A, lda, ipiv, c0, w1);
+    getrf_rec<T>(c, mode, m, ncols, A, lda, ipiv, c0, w1, lb0, lb1, depth + 1);
     c.level--;
+    if (batch) laswp_batch<T>(c, A, lda, c0 + w1, w2, c0, m, inv, w1);
     T *A11 = A + c0 + c0 * lda;
     T *A12 = A + c0 + (c0 + w1) * lda;
     T *A21 = A + (c0 + w1) + c0 * lda;
     T *A22 = A + (c0 + w1) + (c0 + w1) * lda;
     trsm<T, T>(c, mode, 'L', 'L', 'N', 'U', w1, w2, A11, lda, A12, lda);
     gemm<T, T, T>(c, mode, 'N', 'N', 0, m - c0 - w1, w2, w1, -1.0, A21, lda, A12, lda, 1.0, A22, lda);
+    const int *inv2 = batch ? lu_inverse(c, 2 * depth + 1, c0 + w1, m) : nullptr;
     c.level++;
-    getrf_rec<T>(c, mode, m, ncols, A, lda, ipiv, c0 + w1, w2);
+    getrf_rec<T>(c, mode, m, ncols, A, lda, ipiv, c0 + w1, w2, rb0, rb1, depth + 1);
     c.level--;
+    if (batch) laswp_batch<T>(c, A, lda, c0, w1, c0 + w1, m, inv2, w2);
 }
 
 template <typename T>
 void getrf_top(Ctx &c, Mfma mode, long long m, long long n, T *A, long long lda, int *ipiv) {
     const long long mn = m < n ? m : n;
     if (mn <= 0) return;
-    getrf_rec<T>(c, mode, m, n, A, lda, ipiv, 0, mn);
+    // batches when the top node is wide and a column's rows fit the batch kernel
+    c.lu_batch = mn > kLaswpBlock && m <= kLaswpBatchRows;
+    if (c.lu_batch && !c.plan) {
+        c.pv_m = m;
+        c.pv = (int *)scratch(c, 7, (size_t)(3 + 2 * kLaswpDepth) * (size_t)m * sizeof(int));
+        c.pcur = 0;
+        if (!c.pv) { c.lu_batch = false; return; }
+    }
+    int *inv0 = nullptr;
+    if (c.lu_batch) {
+        lu_track_begin(c, m);
+        if (n > mn) inv0 = lu_inverse(c, 2 * kLaswpDepth, 0, m);   // of the identity
+    }
+    getrf_rec<T>(c, mode, m, n, A, lda, ipiv, 0, mn, 0, n, 0);
+    if (c.lu_batch && n > mn) laswp_batch<T>(c, A, lda, mn, n - mn, 0, m, inv0, mn);
+    c.lu_batch = false;
     if (n > m) {
         // U12 = L11⁻¹·(P·A12) for the columns beyond the square part
         trsm<T, T>(c, mode, 'L', 'L', 'N', 'U', m, n - m, A, lda, A + m * lda, lda);

@@ -671,22 +671,38 @@ template void getf2_panel<double>(Ctx &, long long, int, double *, long long, lo
 template void getf2_panel<float>(Ctx &, long long, int, float *, long long, long long, int *);
 
 // ---------------------------------------------------------------------------
-// laswp after a panel: the panel's w interchanges, applied to every column
-// outside the panel. The touched positions are the w diagonal rows and the w
-// pivot rows; position i receives the content that sat at rowsrc[i] before
-// the panel. Each workgroup gathers its columns' touched entries into
-// registers, waits, then scatters them, so repeated pivot rows are harmless.
-// Lanes run over the touched positions, so the w diagonal rows (contiguous
-// in a column) are read and written coalesced.
+// laswp after a panel: the panel's w interchanges, applied to the columns of
+// the current block [blk0, blk1) outside the panel (every column of the
+// matrix when the recursion applies no batches). The touched positions are
+// the w diagonal rows and the w pivot rows; position i receives the content
+// that sat at rowsrc[i] before the panel. Each workgroup gathers its columns'
+// touched entries into registers, waits, then scatters them, so repeated
+// pivot rows are harmless. Lanes run over the touched positions, so the w
+// diagonal rows (contiguous in a column) are read and written coalesced.
+//
+// When the recursion applies interchanges in batches, the trailing
+// workgroups also carry the row tracker forward: P[i] is the original row
+// now at position i, so P_new[i] = P_old[rowsrc[i]] from the panel on
+// (double-buffered, so no workgroup reads an entry another one rewrites).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void laswp_leaf_k(T *__restrict__ A, long long lda, long long c0, int w,
                                                     const int *__restrict__ ipiv,
-                                                    const int *__restrict__ rowsrc, long long ncols,
-                                                    const int *abort) {
-    if (abort && *abort) return;
+                                                    const int *__restrict__ rowsrc, long long blk0,
+                                                    long long nother, int colwg, const int *__restrict__ Pold,
+                                                    int *__restrict__ Pnew, long long m) {
     constexpr int CPB = 32;  // columns per workgroup
     const int tid = threadIdx.x;
+    if ((int)blockIdx.x >= colwg) {
+        // row tracker: 4096 positions per workgroup
+        const long long base = (long long)(blockIdx.x - colwg) * 4096;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const long long i = base + tid + 256 * u;
+            if (i < m) Pnew[i] = Pold[i >= c0 ? rowsrc[i] : i];
+        }
+        return;
+    }
     const int slot = tid & 63, cq = tid >> 6;  // 64 slots × 4 column lanes
     long long pos = -1, srow = -1;
     if (slot < w) {
@@ -701,37 +717,130 @@ __global__ __launch_bounds__(256) void laswp_leaf_k(T *__restrict__ A, long long
 #pragma unroll
     for (int q = 0; q < CPB / 4; ++q) {
         const long long lc = lc0 + q * 4 + cq;
-        const long long col = lc < c0 ? lc : lc + w;
-        if (pos >= 0 && lc < ncols - w && srow != pos) vals[q] = A[srow + col * lda];
+        long long col = blk0 + lc;
+        if (col >= c0) col += w;
+        if (pos >= 0 && lc < nother && srow != pos) vals[q] = A[srow + col * lda];
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < CPB / 4; ++q) {
         const long long lc = lc0 + q * 4 + cq;
-        const long long col = lc < c0 ? lc : lc + w;
-        if (pos >= 0 && lc < ncols - w && srow != pos) A[pos + col * lda] = vals[q];
+        long long col = blk0 + lc;
+        if (col >= c0) col += w;
+        if (pos >= 0 && lc < nother && srow != pos) A[pos + col * lda] = vals[q];
     }
 }
 
 template <typename T>
-void laswp_leaf(Ctx &c, long long ncols_total, T *A, long long lda, long long k0, int w, long long m,
-                const int *ipiv, long long, long long) {
-    if (plan_record(c, PK_LASWP, 2 * w, ncols_total - w, w)) return;
-    const long long others = ncols_total - w;
-    if (others <= 0 || w <= 0) return;
-    (void)m;
-    const int grid = (int)((others + 31) / 32);
+void laswp_leaf(Ctx &c, T *A, long long lda, long long k0, int w, long long m, const int *ipiv, long long blk0,
+                long long blk1) {
+    const long long nother = blk1 - blk0 - w;
+    if (plan_record(c, PK_LASWP, 2 * w, nother, w)) return;
+    if (w <= 0) return;
+    const int colwg = (int)((max(nother, 0LL) + 31) / 32);
+    const int pwg = c.lu_batch ? (int)((m + 4095) / 4096) : 0;
+    if (colwg + pwg == 0) return;
+    const int *Pold = c.lu_batch ? c.pv + (size_t)c.pcur * c.pv_m : nullptr;
+    int *Pnew = c.lu_batch ? c.pv + (size_t)(c.pcur ^ 1) * c.pv_m : nullptr;
     trace_kernel_begin(c);
-    rl_launch(c, laswp_leaf_k<T>, dim3(grid), dim3(256), 0, A, lda, k0, w, ipiv, (const int *)c.rowsrc,
-              ncols_total, (const int *)nullptr);
+    rl_launch(c, laswp_leaf_k<T>, dim3(colwg + pwg), dim3(256), 0, A, lda, k0, w, ipiv, (const int *)c.rowsrc,
+              blk0, max(nother, 0LL), colwg, Pold, Pnew, m);
     RL_CHECK(hipGetLastError());
-    trace_kernel_end(c, PK_LASWP, 0.0, 4.0 * sizeof(T) * w * others);
+    if (c.lu_batch) c.pcur ^= 1;
+    trace_kernel_end(c, PK_LASWP, 0.0, 4.0 * sizeof(T) * w * max(nother, 0LL));
 }
 
-template void laswp_leaf<double>(Ctx &, long long, double *, long long, long long, int, long long,
-                                 const int *, long long, long long);
-template void laswp_leaf<float>(Ctx &, long long, float *, long long, long long, int, long long,
-                                const int *, long long, long long);
+template void laswp_leaf<double>(Ctx &, double *, long long, long long, int, long long, const int *, long long,
+                                 long long);
+template void laswp_leaf<float>(Ctx &, float *, long long, long long, int, long long, const int *, long long,
+                                long long);
+
+// ---------------------------------------------------------------------------
+// Batched interchanges (the recursion's own order: after one half is factored
+// its pivots are applied to the other half's columns in one pass). With the
+// row tracker P (original row at each position) and the inverse of the
+// tracker taken when the batch's pivots began (inv: original row -> its
+// position then), position i of a column must receive the entry that sat at
+// src(i) = inv[P[i]]. A workgroup per column gathers every entry with
+// src(i) != i into registers, waits, then writes them: the touched rows of a
+// wide batch cover most of the column, so its lines are read and written
+// about once each instead of once per interchange.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void lu_iota_k(int *__restrict__ P, long long m) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < m) P[i] = (int)i;
+}
+
+__global__ __launch_bounds__(256) void lu_inverse_k(const int *__restrict__ P, int *__restrict__ inv, long long r0,
+                                                    long long m) {
+    const long long i = r0 + (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < m) inv[P[i]] = (int)i;
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(1024) void laswp_batch_k(T *__restrict__ A, long long lda, long long j0, long long r0,
+                                                      long long m, const int *__restrict__ P,
+                                                      const int *__restrict__ inv) {
+    static_assert(R <= 32, "one bit per row in the mask");
+    T *a = A + (j0 + (long long)blockIdx.x) * lda;
+    const int tid = threadIdx.x;
+    T v[R];
+    unsigned moved = 0u;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const long long i = r0 + tid + 1024LL * r;
+        if (i < m) {
+            const int s = inv[P[i]];
+            if (s != i) { v[r] = a[s]; moved |= 1u << r; }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const long long i = r0 + tid + 1024LL * r;
+        if (moved >> r & 1u) a[i] = v[r];
+    }
+}
+
+void lu_track_begin(Ctx &c, long long m) {
+    if (plan_record(c, PK_OTHER, m, 0, 0)) return;
+    hipLaunchKernelGGL(lu_iota_k, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, c.stream,
+                       c.pv + (size_t)c.pcur * c.pv_m, m);
+    RL_CHECK(hipGetLastError());
+}
+
+int *lu_inverse(Ctx &c, int slot, long long r0, long long m) {
+    if (plan_record(c, PK_OTHER, m - r0, 0, 0)) return nullptr;
+    int *inv = c.pv + (size_t)(2 + slot) * c.pv_m;
+    if (m > r0)
+        hipLaunchKernelGGL(lu_inverse_k, dim3((unsigned)((m - r0 + 255) / 256)), dim3(256), 0, c.stream,
+                           (const int *)(c.pv + (size_t)c.pcur * c.pv_m), inv, r0, m);
+    RL_CHECK(hipGetLastError());
+    return inv;
+}
+
+template <typename T>
+void laswp_batch(Ctx &c, T *A, long long lda, long long j0, long long ncols, long long r0, long long m,
+                 const int *inv, long long npiv) {
+    if (plan_record(c, PK_LASWP, m - r0, ncols, npiv)) return;
+    if (ncols <= 0 || m <= r0) return;
+    const int *P = c.pv + (size_t)c.pcur * c.pv_m;
+    const long long rows = m - r0;
+    trace_kernel_begin(c);
+    if (rows <= 8 * 1024)
+        rl_launch(c, laswp_batch_k<T, 8>, dim3((unsigned)ncols), dim3(1024), 0, A, lda, j0, r0, m, P, inv);
+    else if (rows <= 16 * 1024)
+        rl_launch(c, laswp_batch_k<T, 16>, dim3((unsigned)ncols), dim3(1024), 0, A, lda, j0, r0, m, P, inv);
+    else
+        rl_launch(c, laswp_batch_k<T, 32>, dim3((unsigned)ncols), dim3(1024), 0, A, lda, j0, r0, m, P, inv);
+    RL_CHECK(hipGetLastError());
+    trace_kernel_end(c, PK_LASWP, 0.0, 4.0 * sizeof(T) * npiv * ncols);
+}
+
+template void laswp_batch<double>(Ctx &, double *, long long, long long, long long, long long, long long,
+                                  const int *, long long);
+template void laswp_batch<float>(Ctx &, float *, long long, long long, long long, long long, long long,
+                                 const int *, long long);
 
 // ---------------------------------------------------------------------------
 // Row interchanges of a right-hand-side block (getrs): apply ipiv[k1..k2) in

@@ -141,9 +141,25 @@ def test_getrf_plan_structure():
     panels = [r for r in plan if r[0] == 5]
     assert len(panels) == n // 32 and all(r[3] == 32 for r in panels)
     assert [r[2] for r in panels] == [n - 32 * i for i in range(n // 32)]
+    # every interchange reaches every column outside its own panel exactly
+    # once: leaf records (2w, columns, w), batch records (rows, columns, pivots)
     swaps = [r for r in plan if r[0] == 6]
-    assert len(swaps) == len(panels) and all(r[3] == n - 32 for r in swaps)
+    assert sum(r[4] * r[3] for r in swaps) == sum(r[3] * (n - r[3]) for r in panels)
+    # wide nodes batch their pivots: one batch per half per node wider than 512
+    batches = [r for r in swaps if r[4] > 32]
+    assert len(batches) == 2 * (1 + 2 + 4)          # nodes of width 4096, 2048, 1024
+    assert max(r[3] for r in swaps if r[4] == 32) <= 512 - 32
 
+
+@pytest.mark.parametrize("m,n", [(4096, 4096), (300, 5000), (5000, 300), (2000, 3000), (3000, 2000),
+                                 (65536, 4096), (1000, 1000), (513, 513)])
+def test_getrf_plan_interchanges_reach_every_column_once(m, n):
+    plan = rl.plan("getrf", m, n, 0)
+    panels = [r for r in plan if r[0] == 5]
+    swaps = [r for r in plan if r[0] == 6]
+    assert sum(r[4] * r[3] for r in swaps) == sum(r[3] * (n - r[3]) for r in panels)
+    if m > 32768:
+        assert all(r[4] <= 32 for r in swaps)      # no batches: a column's rows exceed the batch kernel
 
 def test_getrf_plan_rectangular():
     plan = rl.plan("getrf", 5000, 300, 32)
