@@ -13,7 +13,7 @@ namespace rl {
 namespace {
 
 constexpr int kMaxDev = 16;
-constexpr int kScratchSlots = 8;
+constexpr int kScratchSlots = 10;   // 0-6 mixed solver, 7 LU row tracker, 8 correction-solve block inverses
 
 struct DevState {
     bool init = false;

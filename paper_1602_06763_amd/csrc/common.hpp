@@ -138,6 +138,17 @@ template <typename TT, typename TB>
 void trsm(Ctx &c, Mfma mode, char side, char uplo, char trans, char diag, long long m, long long n,
           const TT *T, long long ldt, TB *B, long long ldb);
 
+// Single-launch blocked solve op(T)·X = B for a few right-hand sides; with
+// dinv (the inverses of op(T)'s 64×64 diagonal blocks, from
+// trsv_diag_inverses) each diagonal block is applied as a product instead of
+// a substitution (the refinement's correction solves).
+template <typename TT, typename TB>
+void trsv(Ctx &c, bool lower_eff, bool trans, bool unit, long long m, long long nrhs, const TT *T, long long ldt,
+          TB *B, long long ldb, const double *dinv);
+template <typename TT>
+void trsv_diag_inverses(Ctx &c, bool lower_eff, bool trans, bool unit, long long m, const TT *T, long long ldt,
+                        double *dinv);
+
 // Cholesky / LU recursion (typed over the storage type of the matrix).
 template <typename T>
 void potrf_rec(Ctx &c, Mfma mode, char uplo, long long n, T *A, long long lda, long long off);

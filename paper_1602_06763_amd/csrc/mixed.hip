@@ -15,7 +15,7 @@
 
 namespace rl {
 
-enum ScratchSlot { SL_LP = 0, SL_FULL = 1, SL_VEC = 2, SL_RED = 3, SL_FB = 4, SL_PIV = 5, SL_PERM = 6 };
+enum ScratchSlot { SL_LP = 0, SL_FULL = 1, SL_VEC = 2, SL_RED = 3, SL_FB = 4, SL_PIV = 5, SL_PERM = 6, SL_DINV = 8 };
 
 __global__ void reset_info_k(DevStatus *s) {
     if (threadIdx.x == 0) { s->info = 0; s->error = 0; s->barrier = 0u; }
@@ -272,6 +272,8 @@ struct MixedWork {
     double *part = nullptr;                // row-sum partials
     int *ipiv = nullptr;
     int *perm = nullptr;                   // general: the pivots as a gather map
+    double *dinv1 = nullptr, *dinv2 = nullptr;   // inverted 64×64 diagonal blocks of the two
+                                                 // triangular factors (first and second solve)
 };
 
 static double fetch_scalar(Ctx &c, const double *dptr) {
@@ -424,6 +426,21 @@ static void correction(Ctx &c, bool spd, char uplo, long long n, long long nrhs,
     else
         hipLaunchKernelGGL(perm_scale_rows_k, g, dim3(256), 0, c.stream, n, nrhs, (const int *)w.perm,
                            (const double *)w.s1, (const double *)w.R, n, w.D, n);
+    if (w.dinv1) {
+        // one right-hand side: single-launch blocked solves with the factors'
+        // inverted diagonal blocks (formed once per factorization)
+        if (spd && uplo == 'L') {
+            trsv<float, double>(c, true, false, false, n, nrhs, w.S, n, w.D, n, w.dinv1);
+            trsv<float, double>(c, false, true, false, n, nrhs, w.S, n, w.D, n, w.dinv2);
+        } else if (spd) {
+            trsv<float, double>(c, true, true, false, n, nrhs, w.S, n, w.D, n, w.dinv1);
+            trsv<float, double>(c, false, false, false, n, nrhs, w.S, n, w.D, n, w.dinv2);
+        } else {
+            trsv<float, double>(c, true, false, true, n, nrhs, w.S, n, w.D, n, w.dinv1);
+            trsv<float, double>(c, false, false, false, n, nrhs, w.S, n, w.D, n, w.dinv2);
+        }
+        return;
+    }
     if (spd) {
         if (uplo == 'L') {
             trsm<float, double>(c, Mfma::F64, 'L', 'L', 'N', 'N', n, nrhs, w.S, n, w.D, n);
@@ -435,6 +452,27 @@ static void correction(Ctx &c, bool spd, char uplo, long long n, long long nrhs,
     } else {
         trsm<float, double>(c, Mfma::F64, 'L', 'L', 'N', 'U', n, nrhs, w.S, n, w.D, n);
         trsm<float, double>(c, Mfma::F64, 'L', 'U', 'N', 'N', n, nrhs, w.S, n, w.D, n);
+    }
+}
+
+// The inverted diagonal blocks of both factors, for the single-launch solves
+// of the corrections (same effective triangles as the solves above).
+static void prepare_correction(Ctx &c, bool spd, char uplo, long long n, long long nrhs, MixedWork &w) {
+    if (nrhs != 1 || n <= 2 * kTrsmLeaf) return;   // one right-hand side: the single-launch solve
+    const long long nb = (n + 63) / 64;
+    double *d = (double *)scratch(c, SL_DINV, (size_t)2 * nb * 4096 * sizeof(double));
+    if (!d) return;
+    w.dinv1 = d;
+    w.dinv2 = d + nb * 4096;
+    if (spd && uplo == 'L') {
+        trsv_diag_inverses<float>(c, true, false, false, n, w.S, n, w.dinv1);
+        trsv_diag_inverses<float>(c, false, true, false, n, w.S, n, w.dinv2);
+    } else if (spd) {
+        trsv_diag_inverses<float>(c, true, true, false, n, w.S, n, w.dinv1);
+        trsv_diag_inverses<float>(c, false, false, false, n, w.S, n, w.dinv2);
+    } else {
+        trsv_diag_inverses<float>(c, true, false, true, n, w.S, n, w.dinv1);
+        trsv_diag_inverses<float>(c, false, false, false, n, w.S, n, w.dinv2);
     }
 }
 
@@ -494,6 +532,7 @@ int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const 
     if (lp_info != 0) status = -3;
 
     if (status == 0) {
+        prepare_correction(c, spd, uplo, n, nrhs, w);
         // x0 = A_lp⁻¹·b (as a correction of x = 0, residual r = b)
         hipLaunchKernelGGL(copy_cols_k, dim3(blocks(n), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs, B, ldb,
                            w.R, n);

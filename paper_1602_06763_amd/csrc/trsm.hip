@@ -399,6 +399,7 @@ struct TrsvArgs {
     unsigned long long ticket_base;
     unsigned long long *xw;   // [n][8][2] epoch-tagged halves of x
     DevStatus *st;
+    const double *dinv;       // DINV: inverses of the diagonal blocks of op(T), 64×64 column-major each
 };
 
 __device__ __forceinline__ double rl_readlane(double x, int l) {
@@ -407,7 +408,7 @@ __device__ __forceinline__ double rl_readlane(double x, int l) {
     return __hiloint2double(hi, lo);
 }
 
-template <typename TT, typename TB, int NR>
+template <typename TT, typename TB, int NR, bool DINV>
 __global__ __launch_bounds__(256) void trsv_k(const TT *__restrict__ T, TB *__restrict__ B, TrsvArgs a) {
     __shared__ double tile[3][64][65];
     __shared__ double xs[3][64][NR];
@@ -429,7 +430,17 @@ __global__ __launch_bounds__(256) void trsv_k(const TT *__restrict__ T, TB *__re
     double d[64];      // wave 0: row `lane` of the diagonal block (strictly off-diagonal part)
     double r[NR];      // wave 0: right-hand side, then solution
     double rinv = 1.0;
-    if (wave == 0) {
+    if (wave == 0 && DINV) {
+        // row `lane` of the inverted diagonal block
+        const double *Db = a.dinv + (size_t)pb * 4096;
+#pragma unroll
+        for (int k = 0; k < 64; ++k) d[k] = Db[lane + 64 * k];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) r[q] = (double)B[ri + min(q, nq - 1) * a.ldb];
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int q = 0; q < NR; ++q) r[q] = (lane < nrow && q < nq) ? r[q] : 0.0;
+    } else if (wave == 0) {
 #pragma unroll
         for (int k = 0; k < 64; ++k) {
             const long long c = r0 + min(k, nrow - 1);
@@ -507,14 +518,35 @@ __global__ __launch_bounds__(256) void trsv_k(const TT *__restrict__ T, TB *__re
 #pragma unroll
         for (int q = 0; q < NR; ++q)
             r[q] = lane < nrow ? r[q] + ((red[0][lane][q] + red[1][lane][q]) + red[2][lane][q]) : 0.0;
-        // substitution: x_k = r_k / t_kk, then r_i -= t_ik·x_k on the rows after k
+        if (DINV) {
+            // x = D⁻¹·r: the block's right-hand side through LDS (each lane
+            // overwrites only the row it has just read), four partial sums
 #pragma unroll
-        for (int s = 0; s < 64; ++s) {
-            const int k = fwd ? s : 63 - s;
+            for (int q = 0; q < NR; ++q) red[0][lane][q] = r[q];
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
-                const double xk = rl_readlane(r[q] * rinv, k);
-                r[q] = (lane == k) ? xk : r[q] - d[k] * xk;
+                double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+#pragma unroll
+                for (int k = 0; k < 64; k += 4) {
+                    p0 += d[k] * red[0][k][q];
+                    p1 += d[k + 1] * red[0][k + 1][q];
+                    p2 += d[k + 2] * red[0][k + 2][q];
+                    p3 += d[k + 3] * red[0][k + 3][q];
+                }
+                r[q] = lane < nrow ? (p0 + p1) + (p2 + p3) : 0.0;
+                __builtin_amdgcn_sched_barrier(0);   // one right-hand side's reads in flight at a time
+            }
+        } else {
+            // substitution: x_k = r_k / t_kk, then r_i -= t_ik·x_k on the rows after k
+#pragma unroll
+            for (int s = 0; s < 64; ++s) {
+                const int k = fwd ? s : 63 - s;
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    const double xk = rl_readlane(r[q] * rinv, k);
+                    r[q] = (lane == k) ? xk : r[q] - d[k] * xk;
+                }
             }
         }
         if (lane < nrow) {
@@ -533,9 +565,71 @@ __global__ __launch_bounds__(256) void trsv_k(const TT *__restrict__ T, TB *__re
     }
 }
 
+// ---------------------------------------------------------------------------
+// Inverses of the 64×64 diagonal blocks of op(T) (rows/columns beyond m hold
+// the identity), one workgroup per block: the leaf substitution against the
+// identity, written out in full (zeros included), column-major per block.
+// ---------------------------------------------------------------------------
+template <typename TT, bool LOWER>
+__global__ __launch_bounds__(256) void diag_inv_k(int unit, long long n, const TT *__restrict__ T, long long ti,
+                                                  long long tj, double *__restrict__ dinv) {
+    __shared__ double Nsh[64][65];
+    __shared__ double Xsh[4][64][17];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long r0 = (long long)blockIdx.x * 64;
+    const int t = (int)min(64LL, n - r0);
+    const TT *Tb = T + r0 * ti + r0 * tj;
+    double (*X)[17] = Xsh[wave];
+    {
+        double tv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
+            tv[u] = (double)Tb[min(i, t - 1) * ti + min(j, t - 1) * tj];
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
+            const bool in = i < t && j < t && (LOWER ? (j <= i) : (j >= i));
+            Nsh[i][j] = in ? tv[u] : ((i == j && i >= t) ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = (lane & 15) + 16 * (u & 3), q = (lane >> 4) + 4 * (u >> 2);
+            X[e][q] = (e == 16 * wave + q) ? 1.0 : 0.0;
+        }
+    }
+    __syncthreads();
+    solve64<double, LOWER>(Nsh, X, t, unit, lane);
+    double *Db = dinv + (size_t)blockIdx.x * 4096;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = (lane & 15) + 16 * (u & 3), q = (lane >> 4) + 4 * (u >> 2);
+        Db[e + 64 * (16 * wave + q)] = X[e][q];
+    }
+}
+
+template <typename TT>
+void trsv_diag_inverses(Ctx &c, bool lower_eff, bool trans, bool unit, long long m, const TT *T, long long ldt,
+                        double *dinv) {
+    if (plan_record(c, PK_OTHER, m, 64, 64)) return;
+    const int nb = (int)((m + 63) / 64);
+    if (nb <= 0) return;
+    const long long ti = trans ? ldt : 1, tj = trans ? 1 : ldt;
+    if (lower_eff)
+        hipLaunchKernelGGL((diag_inv_k<TT, true>), dim3(nb), dim3(256), 0, c.stream, (int)unit, m, T, ti, tj, dinv);
+    else
+        hipLaunchKernelGGL((diag_inv_k<TT, false>), dim3(nb), dim3(256), 0, c.stream, (int)unit, m, T, ti, tj, dinv);
+    RL_CHECK(hipGetLastError());
+}
+
+template void trsv_diag_inverses<float>(Ctx &, bool, bool, bool, long long, const float *, long long, double *);
+template void trsv_diag_inverses<double>(Ctx &, bool, bool, bool, long long, const double *, long long, double *);
+
 template <typename TT, typename TB>
-static void trsv(Ctx &c, bool lower_eff, bool trans, bool unit, long long m, long long nrhs, const TT *T,
-                 long long ldt, TB *B, long long ldb) {
+void trsv(Ctx &c, bool lower_eff, bool trans, bool unit, long long m, long long nrhs, const TT *T,
+          long long ldt, TB *B, long long ldb, const double *dinv) {
     const int nb = (int)((m + 63) / 64);
     TrsvWork wk = trsv_work(c, m, nb, (int)((nrhs + 7) / 8));
     if (!wk.xw) return;
@@ -550,10 +644,16 @@ static void trsv(Ctx &c, bool lower_eff, bool trans, bool unit, long long m, lon
         a.ticket_base = wk.ticket_base + (unsigned long long)nb * (unsigned long long)(q0 / 8);
         a.xw = wk.xw;
         a.st = c.dstat;
-        if (a.nrhs == 1)
-            hipLaunchKernelGGL((trsv_k<TT, TB, 1>), dim3(nb), dim3(256), 0, c.stream, T, B + q0 * ldb, a);
-        else
-            hipLaunchKernelGGL((trsv_k<TT, TB, 8>), dim3(nb), dim3(256), 0, c.stream, T, B + q0 * ldb, a);
+        a.dinv = dinv;
+        if (dinv && a.nrhs == 1) {
+            // (the block products are used for one right-hand side at a time;
+            // eight would not fit the registers next to the inverse's row)
+            hipLaunchKernelGGL((trsv_k<TT, TB, 1, true>), dim3(nb), dim3(256), 0, c.stream, T, B + q0 * ldb, a);
+        } else if (a.nrhs == 1) {
+            hipLaunchKernelGGL((trsv_k<TT, TB, 1, false>), dim3(nb), dim3(256), 0, c.stream, T, B + q0 * ldb, a);
+        } else {
+            hipLaunchKernelGGL((trsv_k<TT, TB, 8, false>), dim3(nb), dim3(256), 0, c.stream, T, B + q0 * ldb, a);
+        }
         RL_CHECK(hipGetLastError());
     }
     trace_end(c, PK_TRSM_LEAF, (double)m * m * nrhs, (double)sizeof(TT) * m * m / 2.0 + 16.0 * m * nrhs);
@@ -581,7 +681,7 @@ void trsm(Ctx &c, Mfma mode, char side, char uplo, char trans, char diag, long l
     if (is(side, 'L')) {
         // op(T)·X = B, X m×n, triangle m×m
         if (!c.plan && n <= kTrsvMaxRhs && m > top) {
-            trsv<TT, TB>(c, lowerM, tr, unit, m, n, T, ldt, B, ldb);
+            trsv<TT, TB>(c, lowerM, tr, unit, m, n, T, ldt, B, ldb, nullptr);
             return;
         }
         if (m <= top) {
@@ -625,6 +725,9 @@ void trsm(Ctx &c, Mfma mode, char side, char uplo, char trans, char diag, long l
         }
     }
 }
+
+template void trsv<float, double>(Ctx &, bool, bool, bool, long long, long long, const float *, long long,
+                                  double *, long long, const double *);
 
 template void trsm<double, double>(Ctx &, Mfma, char, char, char, char, long long, long long,
                                    const double *, long long, double *, long long);
