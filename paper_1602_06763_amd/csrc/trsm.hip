@@ -467,21 +467,35 @@ __global__ __launch_bounds__(256) void trsv_k(const TT *__restrict__ T, TB *__re
             const int pj = fwd ? jj : nb - 1 - jj;
             const long long c0 = (long long)pj * 64;
             const int ncol = (int)min(64LL, n - c0);
-            // the tile first: its loads overlap the wait for the block's solution
+            // the tile first, all its loads issued together and complete before
+            // the wait for the block's solution (which arrives later), so no
+            // memory latency sits between that solution and the product
             double mk[64];
             if (!a.trans) {
 #pragma unroll
                 for (int k = 0; k < 64; ++k) mk[k] = (double)T[ri + (c0 + min(k, ncol - 1)) * ldt];
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int k = 0; k < 64; ++k) asm volatile("" : "+v"(mk[k]));
             } else {
-                // op(T)(r, c) = T[c + r*ldt]: lanes over c read contiguously
+                // op(T)(r, c) = T[c + r*ldt]: lanes over c read contiguously,
+                // then the tile is transposed through LDS
                 const long long cl = c0 + min(lane, ncol - 1);
 #pragma unroll
-                for (int rr = 0; rr < 64; ++rr) tile[w][rr][lane] = (double)T[cl + (r0 + min(rr, nrow - 1)) * ldt];
+                for (int rr = 0; rr < 64; ++rr) mk[rr] = (double)T[cl + (r0 + min(rr, nrow - 1)) * ldt];
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int rr = 0; rr < 64; ++rr) tile[w][rr][lane] = mk[rr];
                 __builtin_amdgcn_wave_barrier();
 #pragma unroll
                 for (int k = 0; k < 64; ++k) mk[k] = tile[w][lane][k];
+#pragma unroll
+                for (int k = 0; k < 64; ++k) asm volatile("" : "+v"(mk[k]));
             }
-            if (lane < ncol) {
+            if (lane >= ncol) {
+#pragma unroll
+                for (int q = 0; q < NR; ++q) xs[w][lane][q] = 0.0;   // so the product needs no bounds
+            } else {
                 unsigned long long *src = a.xw + (size_t)(c0 + lane) * 16;
 #pragma unroll
                 for (int q = 0; q < NR; ++q) {
@@ -501,12 +515,23 @@ __global__ __launch_bounds__(256) void trsv_k(const TT *__restrict__ T, TB *__re
                 }
             }
             __builtin_amdgcn_wave_barrier();
+            // the block's solution from LDS in one batch of reads, then the
+            // products in four independent chains
 #pragma unroll
-            for (int k = 0; k < 64; ++k) {
-                if (k < ncol) {
+            for (int q = 0; q < NR; ++q) {
+                double xv[64];
 #pragma unroll
-                    for (int q = 0; q < NR; ++q) acc[q] -= mk[k] * xs[w][k][q];
+                for (int k = 0; k < 64; ++k) xv[k] = xs[w][k][q];
+                asm volatile("" ::: "memory");
+                double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+#pragma unroll
+                for (int k = 0; k < 64; k += 4) {
+                    p0 += mk[k] * xv[k];
+                    p1 += mk[k + 1] * xv[k + 1];
+                    p2 += mk[k + 2] * xv[k + 2];
+                    p3 += mk[k + 3] * xv[k + 3];
                 }
+                acc[q] -= (p0 + p1) + (p2 + p3);
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -526,16 +551,19 @@ __global__ __launch_bounds__(256) void trsv_k(const TT *__restrict__ T, TB *__re
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
+                double rv[64];
+#pragma unroll
+                for (int k = 0; k < 64; ++k) rv[k] = red[0][k][q];
+                asm volatile("" ::: "memory");
                 double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
 #pragma unroll
                 for (int k = 0; k < 64; k += 4) {
-                    p0 += d[k] * red[0][k][q];
-                    p1 += d[k + 1] * red[0][k + 1][q];
-                    p2 += d[k + 2] * red[0][k + 2][q];
-                    p3 += d[k + 3] * red[0][k + 3][q];
+                    p0 += d[k] * rv[k];
+                    p1 += d[k + 1] * rv[k + 1];
+                    p2 += d[k + 2] * rv[k + 2];
+                    p3 += d[k + 3] * rv[k + 3];
                 }
                 r[q] = lane < nrow ? (p0 + p1) + (p2 + p3) : 0.0;
-                __builtin_amdgcn_sched_barrier(0);   // one right-hand side's reads in flight at a time
             }
         } else {
             // substitution: x_k = r_k / t_kk, then r_i -= t_ik·x_k on the rows after k
