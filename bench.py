@@ -41,7 +41,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 matrix (published, dense)
 PEAK_HBM = 8000.0  # GB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_k1_fp64_traffic_potrf_getrf_n16384.md")
-GEMM_SOURCES = [os.path.join(ROOT, "paper_1602_06763_amd", "csrc", f) for f in ("gemm.hip", "common.hpp")]
+GEMM_SOURCES = [os.path.join(ROOT, "paper_1602_06763_amd", "csrc", "gemm.hip")]   # the GEMM kernel's source
 
 
 def parse():

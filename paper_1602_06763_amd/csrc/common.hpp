@@ -70,6 +70,7 @@ struct Ctx {
     // LU with batched interchanges: row tracker (two buffers, current = pcur)
     // and 2·kLaswpDepth + 1 inverse slots, each pv_m ints
     bool lu_batch = false;
+    bool lu_tracked = false;         // the last getrf left its final row tracker at pv + pcur·pv_m
     int *pv = nullptr;
     long long pv_m = 0;
     int pcur = 0;

@@ -97,6 +97,7 @@ static void getrf_rec(Ctx &c, Mfma mode, long long m, long long ncols, T *A, lon
 template <typename T>
 void getrf_top(Ctx &c, Mfma mode, long long m, long long n, T *A, long long lda, int *ipiv) {
     const long long mn = m < n ? m : n;
+    c.lu_tracked = false;
     if (mn <= 0) return;
     // batches when the top node is wide and a column's rows fit the batch kernel
     c.lu_batch = mn > kLaswpBlock && m <= kLaswpBatchRows;
@@ -113,6 +114,7 @@ void getrf_top(Ctx &c, Mfma mode, long long m, long long n, T *A, long long lda,
     }
     getrf_rec<T>(c, mode, m, n, A, lda, ipiv, 0, mn, 0, n, 0);
     if (c.lu_batch && n > mn) laswp_batch<T>(c, A, lda, mn, n - mn, 0, m, inv0, mn);
+    c.lu_tracked = c.lu_batch && !c.plan;
     c.lu_batch = false;
     if (n > m) {
         // U12 = L11⁻¹·(P·A12) for the columns beyond the square part

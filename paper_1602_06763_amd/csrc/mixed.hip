@@ -149,14 +149,35 @@ void scale_ge_f32(Ctx &c, long long n, const double *A, long long lda, double *r
 
 // ---- FP64 residual and backward error ---------------------------------------
 
-// Full symmetric copy of a triangle-stored SPD matrix (for the FP64 residual).
-__global__ void symmetrize_k(long long n, const double *__restrict__ A, long long lda, double *__restrict__ F,
-                             int lower) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long j = blockIdx.y;
-    if (i >= n) return;
-    const bool in = lower ? (i >= j) : (i <= j);
-    F[i + j * n] = in ? A[i + j * lda] : A[j + i * lda];
+// Full symmetric copy of a triangle-stored SPD matrix (for the FP64 residual),
+// by 64×64 tiles of the stored triangle: each tile is read once (coalesced),
+// written in place and, transposed through LDS, into its mirror position.
+__global__ __launch_bounds__(256) void symmetrize_k(long long n, const double *__restrict__ A, long long lda,
+                                                    double *__restrict__ F, int lower) {
+    const long long I = blockIdx.x, J = blockIdx.y;
+    if (lower ? I < J : I > J) return;   // tiles of the stored triangle only
+    __shared__ double S[64][65];
+    const int tid = threadIdx.x, r = tid & 63, c4 = tid >> 6;
+    const long long i0 = I * 64, j0 = J * 64;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int cc = c4 + 4 * u;
+        const long long i = i0 + r, j = j0 + cc;
+        S[r][cc] = (i < n && j < n) ? A[i + j * lda] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int cc = c4 + 4 * u;
+        const long long i = i0 + r, j = j0 + cc;
+        if (i < n && j < n) {
+            if (I != J) F[i + j * n] = S[r][cc];
+            else F[i + j * n] = (lower ? r >= cc : r <= cc) ? S[r][cc] : S[cc][r];
+        }
+        // the mirror tile (J, I): element (j0 + r, i0 + cc) = A(i0 + cc, j0 + r)
+        const long long mi = j0 + r, mj = i0 + cc;
+        if (I != J && mi < n && mj < n) F[mi + mj * n] = S[cc][r];
+    }
 }
 
 __global__ void copy_cols_k(long long n, long long ncol, const double *S, long long lds, double *D,
@@ -176,13 +197,29 @@ __global__ void row_abssum_part_k(long long n, const double *__restrict__ A, lon
     part[(long long)blockIdx.y * n + i] = s;
 }
 
-__global__ __launch_bounds__(256) void inf_norm_finish_k(long long n, long long nchunk, const double *part,
-                                                         double *out) {
+// row sums from the partials (a thread per row), then the largest per workgroup
+__global__ __launch_bounds__(256) void inf_norm_rows_k(long long n, long long nchunk, const double *part,
+                                                       double *bmax) {
+    __shared__ double red[256];
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    double s = 0.0;
+    if (i < n)
+        for (long long q = 0; q < nchunk; ++q) s += part[q * n + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k && (red[threadIdx.x + k] > red[threadIdx.x] || red[threadIdx.x + k] != red[threadIdx.x + k]))
+            red[threadIdx.x] = red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bmax[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void inf_norm_finish_k(long long nb, const double *bmax, double *out) {
     __shared__ double red[256];
     double mx = 0.0;
-    for (long long i = threadIdx.x; i < n; i += 256) {
-        double s = 0.0;
-        for (long long q = 0; q < nchunk; ++q) s += part[q * n + i];
+    for (long long i = threadIdx.x; i < nb; i += 256) {
+        const double s = bmax[i];
         if (s > mx || s != s) mx = s;
     }
     red[threadIdx.x] = mx;
@@ -373,7 +410,11 @@ static void inf_norm(Ctx &c, long long n, const double *A, long long lda, MixedW
     const long long nchunk = (n + 255) / 256;
     hipLaunchKernelGGL(row_abssum_part_k, dim3(blocks(n), (unsigned)nchunk), dim3(256), 0, c.stream, n, A, lda,
                        w.part);
-    hipLaunchKernelGGL(inf_norm_finish_k, dim3(1), dim3(256), 0, c.stream, n, nchunk, w.part, w.scal);
+    double *bmax = w.part + nchunk * n;
+    hipLaunchKernelGGL(inf_norm_rows_k, dim3(blocks(n)), dim3(256), 0, c.stream, n, nchunk, (const double *)w.part,
+                       bmax);
+    hipLaunchKernelGGL(inf_norm_finish_k, dim3(1), dim3(256), 0, c.stream, (long long)blocks(n),
+                       (const double *)bmax, w.scal);
     RL_CHECK(hipGetLastError());
 }
 
@@ -488,7 +529,7 @@ int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const 
     if (spd) w.Af = (double *)scratch(c, SL_FULL, (size_t)n * n * sizeof(double));
     else w.Af = const_cast<double *>(A);
     const long long nchunk = (n + 255) / 256;
-    const size_t vec = (size_t)(2 * n + 2 * n * nrhs + nrhs + 2 + nchunk * n);
+    const size_t vec = (size_t)(2 * n + 2 * n * nrhs + nrhs + 2 + nchunk * n + blocks(n));
     double *v = (double *)scratch(c, SL_VEC, vec * sizeof(double));
     w.ipiv = spd ? nullptr : (ipiv_out ? ipiv_out : (int *)scratch(c, SL_PIV, (size_t)n * sizeof(int)));
     if (!w.S || !w.Af || !v) return -1000 - (int)hipErrorOutOfMemory;
@@ -498,8 +539,8 @@ int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const 
     // scaling + conversion, FP64 copy for the residual, ||A||inf
     if (spd) {
         scale_spd_f32(c, uplo, n, A, lda, w.s1, w.S, n);
-        hipLaunchKernelGGL(symmetrize_k, dim3(blocks(n), (unsigned)n), dim3(256), 0, c.stream, n, A, lda, w.Af,
-                           (int)(uplo == 'L'));
+        const unsigned nt = (unsigned)((n + 63) / 64);
+        hipLaunchKernelGGL(symmetrize_k, dim3(nt, nt), dim3(256), 0, c.stream, n, A, lda, w.Af, (int)(uplo == 'L'));
     } else {
         scale_ge_f32(c, n, A, lda, w.s1, w.s2, w.S, n);
     }
@@ -511,7 +552,10 @@ int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const 
     if (spd) potrf_rec<float>(c, mode, uplo, n, w.S, n, 0);
     else getrf_top<float>(c, mode, n, n, w.S, n, w.ipiv);
     c.abort_on_info = false;
-    if (!spd) {
+    if (!spd && c.lu_tracked) {
+        // the factorization's row tracker is the gather map itself
+        w.perm = c.pv + (size_t)c.pcur * c.pv_m;
+    } else if (!spd) {
         w.perm = (int *)scratch(c, SL_PERM, (size_t)n * sizeof(int));
         if (!w.perm) return -1000 - (int)hipErrorOutOfMemory;
         const size_t shm = n <= 16384 ? (size_t)2 * n * sizeof(int) : 0;
