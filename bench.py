@@ -19,7 +19,9 @@ the dominant kernel, the FP64 matrix-core GEMM on 128×128 tiles.
 ``target_size`` additionally times one dpotrf and one dgetrf at n = 32768
 (``--target-n``), the size at which the FP64 matrix-core fraction is targeted;
 ``spd_inverse`` times dpotri (dtrtri + dlauum of the Cholesky factor) at
-n = 8192 (``--inv-n``).
+n = 8192 (``--inv-n``); ``variants`` times dpotrf with uplo = 'U' and the
+single-precision spotrf / sgetrf at the benchmark size (``--no-variants``
+skips them).
 
 Prints ONE JSON line. ``--gpus N`` with N > 1 exits: this build runs on one GPU.
 ``--copy-calib MB`` only runs a plain device copy of that size 20 times (the
@@ -39,6 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 matrix (published, dense)
+PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 matrix (published, dense)
 PEAK_HBM = 8000.0  # GB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_k1_fp64_traffic_potrf_getrf_n16384.md")
 GEMM_SOURCES = [os.path.join(ROOT, "paper_1602_06763_amd", "csrc", "gemm.hip")]   # the GEMM kernel's source
@@ -55,10 +58,11 @@ def parse():
     p.add_argument("--prec", default="fp16")
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--cpu-n", type=int, default=5120)
+    p.add_argument("--cpu-n", type=int, default=8192)
     p.add_argument("--copy-calib", type=float, default=0.0, help="MB; run only a plain device copy")
     p.add_argument("--target-n", type=int, default=32768,
                    help="also time one dpotrf + dgetrf at this size (0: skip)")
+    p.add_argument("--no-variants", action="store_true", help="skip the uplo = 'U' and FP32 timings")
     p.add_argument("--inv-n", type=int, default=8192,
                    help="also time the SPD inverse (dtrtri + dlauum of a dpotrf factor) at this size (0: skip)")
     return p.parse_args()
@@ -199,6 +203,59 @@ def spd_inverse(n: int, stream, reps: int = 3):
             "trtri_ms": round(mt, 3), "lauum_ms": round(ml, 3),
             "residual_AX_minus_I_rel": resid,
             "flops": "n^3/3 (dtrtri) + n^3/3 (dlauum)"}
+
+
+def variants(n: int, stream, reps: int = 3):
+    """The other instances at the benchmark size: dpotrf with uplo = 'U' on the
+    same SPD input, and the single-precision spotrf / sgetrf (FP32 storage and
+    FP32 matrix cores) on the FP32-rounded inputs; medians of ``reps`` calls
+    after an untimed one, the input restored before each."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1602_06763_amd as rl
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(call, src, dst):
+        ts = []
+        for r in range(reps + 1):
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            e0, e1 = ev(), ev()
+            e0.record(stream)
+            info = call()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            assert info == 0
+            if r:
+                ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    out = {"n": n}
+    A0 = gen.spd_bbt_torch(n, seed=0, device="cuda")
+    A = A0.clone()
+    ms = timed(lambda: rl.potrf(A, "U"), A0, A)
+    out["dpotrf_upper_ms"] = round(ms, 3)
+    out["dpotrf_upper_tflops"] = round(n ** 3 / 3.0 / (ms * 1e-3) / 1e12, 3)
+    S0 = A0.float().T.contiguous().T
+    del A0, A
+    S = S0.clone()
+    ms = timed(lambda: rl.spotrf(S, "L"), S0, S)
+    out["spotrf_ms"] = round(ms, 3)
+    out["spotrf_tflops"] = round(n ** 3 / 3.0 / (ms * 1e-3) / 1e12, 3)
+    del S0, S
+    G0 = gen.general_uniform_torch(n, n, seed=1, device="cuda").float().T.contiguous().T
+    G = G0.clone()
+    piv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    ms = timed(lambda: rl.sgetrf(G, piv), G0, G)
+    out["sgetrf_ms"] = round(ms, 3)
+    out["sgetrf_tflops"] = round(2.0 * n ** 3 / 3.0 / (ms * 1e-3) / 1e12, 3)
+    out["fp32_matrix_peak_tflops"] = PEAK_FP32
+    del G0, G
+    torch.cuda.empty_cache()
+    return out
 
 
 def copy_calibration(mb: float):
@@ -384,6 +441,8 @@ def main():
         out["target_size"] = target_size(args.target_n, stream)
     if args.inv_n > 0:
         out["spd_inverse"] = spd_inverse(args.inv_n, stream)
+    if not args.no_variants:
+        out["variants"] = variants(n, stream)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
     print(json.dumps(out))

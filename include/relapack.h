@@ -224,6 +224,17 @@ void relapack_scale_ge_f32(int n, const double *A, int lda, double *r, double *c
 void relapack_spotrf_lp(char uplo, int n, float *A, int lda, int prec, int *info);
 void relapack_sgetrf_lp(int m, int n, float *A, int lda, int *ipiv, int prec, int *info);
 
+/* ---- single precision (the paper's x = s instances, Sec. 5) ------------ */
+
+/*
+ * FP32 Cholesky / partial-pivoting LU (xpotrf / xgetrf with x = s, Sec. 5):
+ * FP32 storage and FP32 matrix-core updates, otherwise exactly the FP64
+ * routines' recursion, arguments and info (relapack_dpotrf, relapack_dgetrf).
+ * Errors: as relapack_dpotrf / relapack_dgetrf.
+ */
+void relapack_spotrf(char uplo, int n, float *A, int lda, int *info);
+void relapack_sgetrf(int m, int n, float *A, int lda, int *ipiv, int *info);
+
 /* ---- measurement and inspection ------------------------------------------ */
 
 /* Bracket every kernel launch of this thread with HIP events (on = 1) and

@@ -51,6 +51,8 @@ _SIGS = {
     "relapack_scale_spd_f32": ([_c_char, _c_int, _vp, _c_int, _vp, _vp, _c_int, _ip], None),
     "relapack_scale_ge_f32": ([_c_int, _vp, _c_int, _vp, _vp, _vp, _c_int, _ip], None),
     "relapack_spotrf_lp": ([_c_char, _c_int, _vp, _c_int, _c_int, _ip], None),
+    "relapack_spotrf": ([_c_char, _c_int, _vp, _c_int, _ip], None),
+    "relapack_sgetrf": ([_c_int, _c_int, _vp, _c_int, _vp, _ip], None),
     "relapack_sgetrf_lp": ([_c_int, _c_int, _vp, _c_int, _vp, _c_int, _ip], None),
     "relapack_trace_enable": ([_c_int], None),
     "relapack_trace_collect": ([_dp, _c_int], _c_int),
@@ -261,6 +263,21 @@ def sgetrf_lp(A, ipiv, prec=32) -> int:
     info = ctypes.c_int(0)
     lib().relapack_sgetrf_lp(m, n, _ptr(A), _ld(A, m), _ptr(ipiv), PREC.get(prec, prec),
                              ctypes.byref(info))
+    return info.value
+
+
+def spotrf(A, uplo: str = "L", n: int | None = None, lda: int | None = None) -> int:
+    n = A.shape[0] if n is None else n
+    info = ctypes.c_int(0)
+    lib().relapack_spotrf(_b(uplo), n, _ptr(A), _ld(A, n) if lda is None else lda, ctypes.byref(info))
+    return info.value
+
+
+def sgetrf(A, ipiv, m: int | None = None, n: int | None = None, lda: int | None = None) -> int:
+    m = A.shape[0] if m is None else m
+    n = A.shape[1] if n is None else n
+    info = ctypes.c_int(0)
+    lib().relapack_sgetrf(m, n, _ptr(A), _ld(A, m) if lda is None else lda, _ptr(ipiv), ctypes.byref(info))
     return info.value
 
 

@@ -551,6 +551,18 @@ void relapack_sgetrf_lp(int m, int n, float *A, int lda, int *ipiv, int prec, in
     *info = call_end(c);
 }
 
+// ---- FP32 factorizations (FP32 storage, FP32 matrix-core updates) ---------
+
+void relapack_spotrf(char uplo, int n, float *A, int lda, int *info) {
+    if (!info) return;
+    relapack_spotrf_lp(uplo, n, A, lda, 32, info);
+}
+
+void relapack_sgetrf(int m, int n, float *A, int lda, int *ipiv, int *info) {
+    if (!info) return;
+    relapack_sgetrf_lp(m, n, A, lda, ipiv, 32, info);
+}
+
 // ---- triangular product, inverse, SPD inverse ------------------------------
 
 void relapack_dtrmm(char side, char uplo, char transa, char diag, int m, int n, double alpha,

@@ -1,0 +1,86 @@
+"""The single-precision instances (relapack_spotrf, relapack_sgetrf: FP32
+storage, FP32 matrix-core updates) through the C ABI: exact integer and dyadic
+constructions come back bit for bit (every value and partial sum is exact in
+binary32), random inputs against the FP64 oracle within FP32 rounding, the
+residual bounds with u = 2^-24, and LAPACK's info on failure."""
+import numpy as np
+import pytest
+
+import gen
+import paper_1602_06763_amd as rl
+from gpu_util import U32, ipiv_dev, rel_fro, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _f32(a):
+    return np.asfortranarray(np.asarray(a, dtype=np.float32))
+
+
+@pytest.mark.parametrize("n", [1, 64, 257, 1000])
+def test_spotrf_exact_integer_factor(n):
+    a, lo = gen.exact_chol(n, seed=n)
+    A = to_dev(_f32(a))
+    assert rl.spotrf(A, "L") == 0
+    assert np.array_equal(np.tril(to_host(A)).astype(np.float64), lo)
+
+
+@pytest.mark.parametrize("n", [2, 65, 300, 1031])
+@pytest.mark.parametrize("uplo", ["L", "U"])
+def test_spotrf_vs_oracle(orc, n, uplo):
+    a = gen.spd_bbt(n, seed=n + 1)
+    ref, info = orc.potrf(a, uplo)
+    assert info == 0
+    A = to_dev(_f32(a), ld=n + 1)
+    assert rl.spotrf(A, uplo, n=n, lda=n + 1) == 0
+    tri = np.tril if uplo == "L" else np.triu
+    got = tri(to_host(A).astype(np.float64))
+    assert rel_fro(got, tri(ref)) <= 4 * n * U32
+    F = got if uplo == "L" else got.T
+    assert np.linalg.norm(F @ F.T - a) / np.linalg.norm(a) <= 10 * n * U32
+
+
+def test_spotrf_not_positive_definite():
+    a = gen.spd_bbt(300, seed=5)
+    a[200, 200] = -1.0
+    A = to_dev(_f32(a))
+    assert rl.spotrf(A, "L") == 201
+
+
+@pytest.mark.parametrize("m,n", [(300, 300), (2000, 700), (700, 2000), (1000, 1000)])
+def test_sgetrf_exact_dyadic(m, n):
+    a, perm, lo, up = gen.exact_lu(m, n, seed=m + 3 * n)
+    A = to_dev(_f32(a))
+    k = min(m, n)
+    piv = ipiv_dev(k)
+    assert rl.sgetrf(A, piv) == 0
+    ipiv_ref, rows = gen.exact_lu_pivots(perm, k)
+    assert np.array_equal(piv.cpu().numpy()[:k], ipiv_ref)
+    f = to_host(A).astype(np.float64)
+    assert np.array_equal(np.tril(f[:, :k], -1) + np.eye(m, k), lo[rows])
+    assert np.array_equal(np.triu(f[:k, :]), up)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (33, 33), (600, 600), (1500, 40), (513, 700), (2000, 2000)])
+def test_sgetrf_random_residual(orc, m, n):
+    a = gen.general_uniform(m, n, seed=m + n)
+    A = to_dev(_f32(a), ld=m + 2)
+    k = min(m, n)
+    piv = ipiv_dev(k)
+    assert rl.sgetrf(A, piv, m=m, n=n, lda=m + 2) == 0
+    ip = piv.cpu().numpy()[:k]
+    assert ((ip >= np.arange(1, k + 1)) & (ip <= m)).all()
+    f = to_host(A).astype(np.float64)
+    L, U = orc.unpack_lu(f)
+    assert np.abs(L).max() <= 1.0
+    pa = orc.apply_ipiv(a.astype(np.float32).astype(np.float64), ip)
+    bound = 10 * max(m, n) * U32 * np.linalg.norm(np.abs(L) @ np.abs(U))
+    assert np.linalg.norm(pa - L @ U) <= bound
+
+
+def test_sgetrf_zero_pivot_completes():
+    a = gen.general_uniform(200, 200, seed=3)
+    a[:, 50] = 0.0
+    A = to_dev(_f32(a))
+    piv = ipiv_dev(200)
+    assert rl.sgetrf(A, piv) == 51
