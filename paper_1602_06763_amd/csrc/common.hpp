@@ -67,8 +67,8 @@ struct Ctx {
     DevStatus *hstat = nullptr;      // pinned host mirror
     int *rowsrc = nullptr;
     size_t rowsrc_elems = 0;
-    // LU with batched interchanges: row tracker (two buffers, current = pcur)
-    // and 2·kLaswpDepth + 1 inverse slots, each pv_m ints
+    // LU with batched interchanges: row tracker (two buffers, current = pcur),
+    // 2·kLaswpDepth + 1 inverse slots and one batch source map, each pv_m ints
     bool lu_batch = false;
     bool lu_tracked = false;         // the last getrf left its final row tracker at pv + pcur·pv_m
     int *pv = nullptr;

@@ -18,7 +18,8 @@
 //    matrix cores work on the current one.
 //  * XCD-aware launch: workgroup b runs on XCD b % 8; logical tiles are dealt
 //    out so that each XCD gets a contiguous run of them, and tiles are ordered
-//    in groups of 8 tile-rows so that neighbours share A panels in that XCD's L2.
+//    in groups of 8 tile-rows (triangles: bands of 8 tile rows, column by
+//    column) so that neighbours share operand panels in that XCD's L2.
 //  * FP64 (v_mfma_f64_16x16x4f64) and FP32 (v_mfma_f32_16x16x4f32) operands;
 //    the operand type in LDS (TL) may differ from the storage types, e.g. FP32
 //    factors multiplied in FP64 during iterative refinement.
@@ -70,6 +71,33 @@ __device__ __forceinline__ int xcd_logical(int bid, int grid) {
     return (bid & 7) * per + (bid >> 3);
 }
 
+// Logical tile -> (t, u), t >= u, of a T×T lower tile triangle: bands of 8
+// tile rows, each band column by column (first its full 8-row part, then its
+// own lower triangle), so that consecutive tiles, which the launch keeps on
+// one XCD, form 8×8 blocks as in the full grid and share operand panels in
+// that XCD's L2.
+__device__ __forceinline__ void tri_band_tile(int tile, int T, int &t, int &u) {
+    int b = 0, start = 0, h = 0;
+    while (true) {
+        h = min(8, T - 8 * b);
+        const int sz = h * 8 * b + h * (h + 1) / 2;
+        if (tile < start + sz) break;
+        start += sz;
+        ++b;
+    }
+    int r = tile - start;
+    if (r < h * 8 * b) {
+        u = r / h;
+        t = 8 * b + r % h;
+    } else {
+        r -= h * 8 * b;
+        int c = 0;
+        while (r >= h - c) { r -= h - c; ++c; }
+        u = 8 * b + c;
+        t = u + r;
+    }
+}
+
 template <typename TL, typename TA, typename TB, typename TC, bool TRA, bool TRB, int TRI, int BM,
           int BN>
 __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
@@ -95,11 +123,8 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
         tm = first + r % gm;
         tn = r / gm;
     } else {
-        // row-major enumeration of the lower tile triangle: tile = tm(tm+1)/2 + tn
-        int t = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
-        while ((t + 1) * (t + 2) / 2 <= tile) ++t;
-        while (t * (t + 1) / 2 > tile) --t;
-        const int u = tile - t * (t + 1) / 2;
+        int t, u;
+        tri_band_tile(tile, g.tiles_m, t, u);
         if (TRI == 1) { tm = t; tn = u; }   // lower: tm >= tn
         else { tm = u; tn = t; }            // upper: tm <= tn
     }
@@ -323,10 +348,8 @@ __global__ __launch_bounds__(256) void gemm_k8(GemmArgs<float, float, float> g) 
         tm = first + r % gm;
         tn = r / gm;
     } else {
-        int t = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
-        while ((t + 1) * (t + 2) / 2 <= tile) ++t;
-        while (t * (t + 1) / 2 > tile) --t;
-        const int u = tile - t * (t + 1) / 2;
+        int t, u;
+        tri_band_tile(tile, g.tiles_m, t, u);
         if (TRI == 1) { tm = t; tn = u; }
         else { tm = u; tn = t; }
     }

@@ -777,10 +777,16 @@ __global__ __launch_bounds__(256) void lu_inverse_k(const int *__restrict__ P, i
     if (i < m) inv[P[i]] = (int)i;
 }
 
+// the batch's source of every position, once for all of its columns
+__global__ __launch_bounds__(256) void lu_src_k(const int *__restrict__ P, const int *__restrict__ inv,
+                                                int *__restrict__ src, long long r0, long long m) {
+    const long long i = r0 + (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < m) src[i] = inv[P[i]];
+}
+
 template <typename T, int R>
 __global__ __launch_bounds__(1024) void laswp_batch_k(T *__restrict__ A, long long lda, long long j0, long long r0,
-                                                      long long m, const int *__restrict__ P,
-                                                      const int *__restrict__ inv) {
+                                                      long long m, const int *__restrict__ srcp) {
     static_assert(R <= 32, "one bit per row in the mask");
     T *a = A + (j0 + (long long)blockIdx.x) * lda;
     const int tid = threadIdx.x;
@@ -790,7 +796,7 @@ __global__ __launch_bounds__(1024) void laswp_batch_k(T *__restrict__ A, long lo
     for (int r = 0; r < R; ++r) {
         const long long i = r0 + tid + 1024LL * r;
         if (i < m) {
-            const int s = inv[P[i]];
+            const int s = srcp[i];
             if (s != i) { v[r] = a[s]; moved |= 1u << r; }
         }
     }
@@ -825,14 +831,16 @@ void laswp_batch(Ctx &c, T *A, long long lda, long long j0, long long ncols, lon
     if (plan_record(c, PK_LASWP, m - r0, ncols, npiv)) return;
     if (ncols <= 0 || m <= r0) return;
     const int *P = c.pv + (size_t)c.pcur * c.pv_m;
+    int *src = c.pv + (size_t)(3 + 2 * kLaswpDepth) * c.pv_m;
     const long long rows = m - r0;
+    hipLaunchKernelGGL(lu_src_k, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, c.stream, P, inv, src, r0, m);
     trace_kernel_begin(c);
     if (rows <= 8 * 1024)
-        rl_launch(c, laswp_batch_k<T, 8>, dim3((unsigned)ncols), dim3(1024), 0, A, lda, j0, r0, m, P, inv);
+        rl_launch(c, laswp_batch_k<T, 8>, dim3((unsigned)ncols), dim3(1024), 0, A, lda, j0, r0, m, (const int *)src);
     else if (rows <= 16 * 1024)
-        rl_launch(c, laswp_batch_k<T, 16>, dim3((unsigned)ncols), dim3(1024), 0, A, lda, j0, r0, m, P, inv);
+        rl_launch(c, laswp_batch_k<T, 16>, dim3((unsigned)ncols), dim3(1024), 0, A, lda, j0, r0, m, (const int *)src);
     else
-        rl_launch(c, laswp_batch_k<T, 32>, dim3((unsigned)ncols), dim3(1024), 0, A, lda, j0, r0, m, P, inv);
+        rl_launch(c, laswp_batch_k<T, 32>, dim3((unsigned)ncols), dim3(1024), 0, A, lda, j0, r0, m, (const int *)src);
     RL_CHECK(hipGetLastError());
     trace_kernel_end(c, PK_LASWP, 0.0, 4.0 * sizeof(T) * npiv * ncols);
 }
