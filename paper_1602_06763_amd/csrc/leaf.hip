@@ -263,13 +263,6 @@ __device__ __forceinline__ unsigned wave_min_u32(unsigned x) {
     x = min(x, dpp_u32<0x140>(x));
     return min(min(rlane(x, 0), rlane(x, 16)), min(rlane(x, 32), rlane(x, 48)));
 }
-// 64-bit maximum in two 32-bit passes: the high halves, then the low halves
-// of the lanes that hold the largest high half.
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
-    const unsigned hi = wave_max_u32((unsigned)(x >> 32));
-    const unsigned lo = wave_max_u32((unsigned)(x >> 32) == hi ? (unsigned)x : 0u);
-    return ((unsigned long long)hi << 32) | lo;
-}
 // Candidate key: 0 for "no candidate" (retired, out of range or NaN), else
 // the bit pattern of the non-negative magnitude plus one, so keys order like
 // magnitudes and key 1 is an exact zero.
@@ -282,9 +275,22 @@ __device__ __forceinline__ bool cand_wins(unsigned long long k2, unsigned p2, un
 }
 // The wave's winning lane (-1 if no lane has a candidate) with its key and
 // position. Positions are only compared when keys tie exactly. Uniform
-// control flow throughout (readlane).
+// control flow throughout (readlane). The 64-bit maximum takes the high
+// halves first; a unique largest high half (the usual case for data that are
+// not exact ties) already names the winner, else the low halves of the lanes
+// that share it decide.
 __device__ __forceinline__ int wave_winner(unsigned long long key, unsigned pos, unsigned long long &wk, unsigned &wp) {
-    wk = wave_max_u64(key);
+    const unsigned khi = (unsigned)(key >> 32);
+    const unsigned hi = wave_max_u32(khi);
+    const unsigned long long bh = __ballot(khi == hi);
+    if (__builtin_popcountll(bh) == 1) {
+        // hi exceeds every other lane's high half, so it is nonzero: a candidate
+        const int wl = (int)__builtin_ctzll(bh);
+        wk = ((unsigned long long)hi << 32) | rlane((unsigned)key, wl);
+        wp = rlane(pos, wl);
+        return wl;
+    }
+    wk = ((unsigned long long)hi << 32) | wave_max_u32(khi == hi ? (unsigned)key : 0u);
     const bool mine = key == wk && key != 0;
     const unsigned long long ball = __ballot(mine);
     if (ball == 0) { wp = 0xFFFFFFFFu; return -1; }
@@ -405,6 +411,7 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
             if (cand_wins(S.rk[0][q], S.rp[0][q], bk, bp)) { bk = S.rk[0][q]; bp = S.rp[0][q]; bc = S.rc[0][q][0]; bwv = q; }
 
         int src_g = -1;   // workgroup whose record holds the pivot row (G > 1)
+        T spiv = T(0);    // the winner's first window entry, from the staged records
         if (G > 1) {
             // publish this workgroup's candidate: one word per thread
             unsigned long long *mine = a.rec + ((size_t)j * kRecSlots + g) * kRecWords;
@@ -429,10 +436,15 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
                 for (int q = 0; q < NQ; ++q)
                     wpq[q] = &a.rec[((size_t)j * kRecSlots + min(wave + 4 * q, G - 1)) * kRecWords + 4 +
                                     min(lane, nwin - 1)];
+                // words of workgroups that do not exist are not loaded (they read as fresh)
                 auto issue = [&](unsigned long long &h, unsigned long long *wv) {
-                    h = subw(hp);
+                    h = ET;
+                    if (tid < 4 * G) h = subw(hp);
 #pragma unroll
-                    for (int q = 0; q < NQ; ++q) wv[q] = subw(wpq[q]);
+                    for (int q = 0; q < NQ; ++q) {
+                        wv[q] = ET;
+                        if (wave + 4 * q < G) wv[q] = subw(wpq[q]);
+                    }
                 };
                 auto fresh = [&](unsigned long long h, const unsigned long long *wv) {
                     bool ok = tid >= 4 * G || (unsigned)(h >> 32) == E;
@@ -464,11 +476,13 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
                 unsigned long long tk = 0;
                 unsigned tp = 0xFFFFFFFFu;
                 int tc = -1;
+                T w0 = T(0);
                 if (lane < G) {
                     const unsigned *h = &stage[lane * kRecWords];
                     tk = ((unsigned long long)h[1] << 32) | h[0];
                     tp = h[2];
                     tc = (int)h[3];
+                    w0 = reinterpret_cast<const T *>(&stage[lane * kRecWords + 4])[0];
                 }
                 unsigned long long gk2;
                 unsigned gp2;
@@ -476,6 +490,7 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
                 bk = gk2;
                 bp = gp2;
                 bc = __builtin_amdgcn_readlane(tc, gl < 0 ? 0 : gl);
+                spiv = lane_bcast(w0, gl < 0 ? 0 : gl);
                 src_g = gl;
             } else {
             // every workgroup's header, one per thread
@@ -582,40 +597,40 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
             pvs[j] = p;
             if (!nz && zfirst < 0) zfirst = j;
         }
-        const T piv = u[0];
+        // the rest of the pivot window is read while the multipliers are formed
+        T uc[W - 1];
+#pragma unroll
+        for (int q = 0; q < W - 1; ++q) uc[q] = u[q + 1];
+        const T piv = (G > 1 && G <= kPanelStageG && !useD) ? spiv : u[0];
 
-        // -- retire the pivot content, move row d's, scale the rest
+        // -- scale the live rows, retire the pivot content, move row d's
         T lk[2];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int r = tid + 256 * k;
             const bool ret = act[k] && (useD ? pos[k] == d : cid[k] == bc);
-            lk[k] = T(0);
+            const bool sc = act[k] && !ret;
+            const T l = nz ? x[k][0] / piv : x[k][0];
+            lk[k] = sc ? l : T(0);
+            if (sc) {
+                if (!useD && pos[k] == d) pos[k] = p;
+                F[r * kPanelLds + j] = l;
+            }
             if (ret) {
 #pragma unroll
                 for (int q = 0; q < W; ++q) Urow[j][q] = x[k][q];
                 act[k] = false;
                 pos[k] = d;
                 rstep[k] = j;
-            } else if (act[k]) {
-                if (!useD && pos[k] == d) pos[k] = p;
-                const T l = nz ? x[k][0] / piv : x[k][0];
-                F[r * kPanelLds + j] = l;
-                lk[k] = l;
             }
         }
         // x[q] <- x[q+1] - l·u[q+1] over the whole window: entries past the
         // live columns are never read, and a branch here would make the
         // compiler copy the window between registers at every step
-        {
-            T uc[W - 1];
 #pragma unroll
-            for (int q = 0; q < W - 1; ++q) uc[q] = u[q + 1];
+        for (int k = 0; k < 2; ++k)
 #pragma unroll
-            for (int k = 0; k < 2; ++k)
-#pragma unroll
-                for (int q = 0; q < W - 1; ++q) x[k][q] = x[k][q + 1] - lk[k] * uc[q];
-        }
+            for (int q = 0; q < W - 1; ++q) x[k][q] = x[k][q + 1] - lk[k] * uc[q];
     }
     __syncthreads();
     if (g == 0) {
