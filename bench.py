@@ -23,7 +23,7 @@ n = 8192 (``--inv-n``); ``variants`` times dpotrf with uplo = 'U' and the
 single-precision spotrf / sgetrf at the benchmark size (``--no-variants``
 skips them).
 
-Prints ONE JSON line. ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line. ``--gpus N`` with N > 1 exits: the library runs on one GPU.
 ``--copy-calib MB`` only runs a plain device copy of that size 20 times (the
 reference point for the HBM byte counters) and prints nothing else.
 """
@@ -272,7 +272,7 @@ def copy_calibration(mb: float):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.copy_calib > 0:
