@@ -59,6 +59,7 @@ def parse():
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-n", type=int, default=8192)
+    p.add_argument("--cpu-n1", type=int, default=2048, help="size of the one-thread oracle sample (0 skips it)")
     p.add_argument("--copy-calib", type=float, default=0.0, help="MB; run only a plain device copy")
     p.add_argument("--target-n", type=int, default=32768,
                    help="also time one dpotrf + dgetrf at this size (0: skip)")
@@ -92,14 +93,10 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(n: int):
-    """The oracle (unblocked FP64 Cholesky + partial-pivoting LU) on one n×n
-    instance of each workload, on this host's cores."""
+def _oracle_pass(n: int):
     import gen
     import oracle
 
-    oracle.build(force=False)
-    threads = oracle.get_threads()
     a = gen.spd_bbt(n, seed=0)
     g = gen.general_uniform(n, n, seed=0)
     t0 = time.perf_counter()
@@ -109,9 +106,30 @@ def cpu_baseline(n: int):
     t2 = time.perf_counter()
     assert i1 == 0 and i2 == 0
     flops = n ** 3 / 3.0 + 2.0 * n ** 3 / 3.0
-    return {"value": flops / (t2 - t0) / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle dpotrf + dgetrf, one n={n} instance each (same generators), "
-                      f"{t1 - t0:.1f} s + {t2 - t1:.1f} s"}
+    return flops / (t2 - t0) / 1e12, t1 - t0, t2 - t1
+
+
+def cpu_baseline(n: int, n1: int):
+    """The oracle (unblocked FP64 Cholesky + partial-pivoting LU) on one n×n
+    instance of each workload on all of this host's cores, and on one n1×n1
+    instance of each with one thread."""
+    import oracle
+
+    oracle.build(force=False)
+    threads = oracle.get_threads()
+    v, tp, tg = _oracle_pass(n)
+    out = {"value": v, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": f"oracle dpotrf + dgetrf, one n={n} instance each (same generators), "
+                     f"{tp:.1f} s + {tg:.1f} s"}
+    if n1 > 0:
+        oracle.set_threads(1)
+        try:
+            v1, tp1, tg1 = _oracle_pass(n1)
+        finally:
+            oracle.set_threads(threads)
+        out["single_core"] = {"value": v1, "unit": "TFLOP/s", "cores": 1,
+                              "sample": f"one n={n1} instance each, {tp1:.1f} s + {tg1:.1f} s"}
+    return out
 
 
 def target_size(n: int, stream):
@@ -397,6 +415,11 @@ def main():
                     "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) if v["ms"] > 0 and v["flops"] > 0 else None,
                     "gbps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 and v["bytes"] > 0 else None}
                 for k, v in fam.items()}
+    # the leaves' pivot chains are latency-bound: time per factored column
+    # (every column of the matrix passes through exactly one potf2 and one LU panel)
+    for k in ("potf2", "getf2_panel"):
+        if k in families:
+            families[k]["us_per_column"] = round(fam[k]["ms"] * 1e3 / n, 3)
 
     out = {
         "metric": "dpotrf/dgetrf TFLOP/s at n=16384; mixed+IR vs FP64 solve speedup at 1e-14",
@@ -444,7 +467,7 @@ def main():
     if not args.no_variants:
         out["variants"] = variants(n, stream)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_n1)
     print(json.dumps(out))
 
 
