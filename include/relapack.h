@@ -235,6 +235,42 @@ void relapack_sgetrf_lp(int m, int n, float *A, int lda, int *ipiv, int prec, in
 void relapack_spotrf(char uplo, int n, float *A, int lda, int *info);
 void relapack_sgetrf(int m, int n, float *A, int lda, int *ipiv, int *info);
 
+/* ---- batched factorizations ---------------------------------------------- */
+
+/*
+ * Cholesky of `count` independent SPD matrices of uneven sizes in one launch
+ * (the recursive xpotrf of Sec. 3 and Sec. 5 per matrix, run on the device,
+ * one workgroup per matrix). Matrix b is n[b]×n[b] at A[b] with leading
+ * dimension lda[b], column-major; uplo as in relapack_dpotrf (only that
+ * triangle is read and written).
+ *   n, A, lda, info: DEVICE arrays of `count` entries (A: device pointers to
+ *   the caller's device matrices); the caller owns all of them.
+ *   info[b] (device): 0, k > 0 (leading minor k not positive definite; that
+ *   matrix's factorization stopped there), -2 (n[b] < 0 or n[b] > 512),
+ *   -4 (lda[b] < max(1, n[b])).
+ * Returns 0, -1 (uplo), -2 (count < 0), -3 (a null array with count > 0),
+ * or -1000 - hipError_t. Stream-ordered; returns after completion.
+ */
+int relapack_dpotrf_batched(char uplo, int count, const int *n, double *const *A, const int *lda, int *info);
+int relapack_spotrf_batched(char uplo, int count, const int *n, float *const *A, const int *lda, int *info);
+
+/*
+ * LU with partial pivoting of `count` independent square matrices of uneven
+ * sizes in one launch (the recursive xgetrf of Sec. 3 and Sec. 5 per matrix,
+ * on the device, one workgroup per matrix): P·A = L·U with LAPACK's ipiv.
+ *   n, A, lda, ipiv, info: DEVICE arrays of `count` entries; ipiv[b] points
+ *   to the caller's device array of n[b] ints (1-based pivot rows).
+ *   info[b] (device): 0, k > 0 (U(k,k) exactly zero, the first such k; the
+ *   factorization completes), -2 (n[b] < 0 or n[b] > 256), -4 (lda[b] <
+ *   max(1, n[b])).
+ * Returns 0, -1 (count < 0), -2 (a null array with count > 0), or
+ * -1000 - hipError_t. Stream-ordered; returns after completion.
+ */
+int relapack_dgetrf_batched(int count, const int *n, double *const *A, const int *lda, int *const *ipiv,
+                            int *info);
+int relapack_sgetrf_batched(int count, const int *n, float *const *A, const int *lda, int *const *ipiv,
+                            int *info);
+
 /* ---- measurement and inspection ------------------------------------------ */
 
 /* Bracket every kernel launch of this thread with HIP events (on = 1) and

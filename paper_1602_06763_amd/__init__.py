@@ -54,6 +54,10 @@ _SIGS = {
     "relapack_spotrf": ([_c_char, _c_int, _vp, _c_int, _ip], None),
     "relapack_sgetrf": ([_c_int, _c_int, _vp, _c_int, _vp, _ip], None),
     "relapack_sgetrf_lp": ([_c_int, _c_int, _vp, _c_int, _vp, _c_int, _ip], None),
+    "relapack_dpotrf_batched": ([_c_char, _c_int, _vp, _vp, _vp, _vp], _c_int),
+    "relapack_spotrf_batched": ([_c_char, _c_int, _vp, _vp, _vp, _vp], _c_int),
+    "relapack_dgetrf_batched": ([_c_int, _vp, _vp, _vp, _vp, _vp], _c_int),
+    "relapack_sgetrf_batched": ([_c_int, _vp, _vp, _vp, _vp, _vp], _c_int),
     "relapack_trace_enable": ([_c_int], None),
     "relapack_trace_collect": ([_dp, _c_int], _c_int),
     "relapack_plan": ([ctypes.c_char_p, _c_ll, _c_ll, _c_int, _llp, _c_ll], _c_ll),
@@ -271,6 +275,19 @@ def spotrf(A, uplo: str = "L", n: int | None = None, lda: int | None = None) -> 
     info = ctypes.c_int(0)
     lib().relapack_spotrf(_b(uplo), n, _ptr(A), _ld(A, n) if lda is None else lda, ctypes.byref(info))
     return info.value
+
+
+def potrf_batched(uplo: str, count: int, n, A_ptrs, lda, info, single: bool = False) -> int:
+    """Batched Cholesky: n, lda, info are device int32 arrays, A_ptrs a device int64 array of matrix
+    addresses (count entries each). Returns the call status; per-matrix info lands in `info`."""
+    f = lib().relapack_spotrf_batched if single else lib().relapack_dpotrf_batched
+    return f(_b(uplo), count, _ptr(n), _ptr(A_ptrs), _ptr(lda), _ptr(info))
+
+
+def getrf_batched(count: int, n, A_ptrs, lda, ipiv_ptrs, info, single: bool = False) -> int:
+    """Batched LU: as potrf_batched, with ipiv_ptrs a device int64 array of int32 pivot-array addresses."""
+    f = lib().relapack_sgetrf_batched if single else lib().relapack_dgetrf_batched
+    return f(count, _ptr(n), _ptr(A_ptrs), _ptr(lda), _ptr(ipiv_ptrs), _ptr(info))
 
 
 def sgetrf(A, ipiv, m: int | None = None, n: int | None = None, lda: int | None = None) -> int:

@@ -257,6 +257,35 @@ static inline bool is(char a, char b) { return a == b || a == (char)(b + ('a' - 
 
 using namespace rl;
 
+namespace rl {
+
+template <typename T>
+static int potrf_batched_call(char uplo, int count, const int *n, T *const *A, const int *lda, int *info) {
+    if (!is(uplo, 'L') && !is(uplo, 'U')) return -1;
+    if (count < 0) return -2;
+    if (count == 0) return 0;
+    if (!n || !A || !lda || !info) return -3;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) return call_end(c);
+    potrf_batched<T>(c, is(uplo, 'U'), count, n, A, lda, info);
+    const int r = call_end(c);
+    return r < 0 ? r : 0;
+}
+
+template <typename T>
+static int getrf_batched_call(int count, const int *n, T *const *A, const int *lda, int *const *ipiv, int *info) {
+    if (count < 0) return -1;
+    if (count == 0) return 0;
+    if (!n || !A || !lda || !ipiv || !info) return -2;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) return call_end(c);
+    getrf_batched<T>(c, count, n, A, lda, ipiv, info);
+    const int r = call_end(c);
+    return r < 0 ? r : 0;
+}
+
+}  // namespace rl
+
 extern "C" {
 
 int relapack_version(void) { return 1; }
@@ -561,6 +590,23 @@ void relapack_spotrf(char uplo, int n, float *A, int lda, int *info) {
 void relapack_sgetrf(int m, int n, float *A, int lda, int *ipiv, int *info) {
     if (!info) return;
     relapack_sgetrf_lp(m, n, A, lda, ipiv, 32, info);
+}
+
+// ---- batched factorizations ------------------------------------------------
+
+int relapack_dpotrf_batched(char uplo, int count, const int *n, double *const *A, const int *lda, int *info) {
+    return rl::potrf_batched_call<double>(uplo, count, n, A, lda, info);
+}
+int relapack_spotrf_batched(char uplo, int count, const int *n, float *const *A, const int *lda, int *info) {
+    return rl::potrf_batched_call<float>(uplo, count, n, A, lda, info);
+}
+int relapack_dgetrf_batched(int count, const int *n, double *const *A, const int *lda, int *const *ipiv,
+                            int *info) {
+    return rl::getrf_batched_call<double>(count, n, A, lda, ipiv, info);
+}
+int relapack_sgetrf_batched(int count, const int *n, float *const *A, const int *lda, int *const *ipiv,
+                            int *info) {
+    return rl::getrf_batched_call<float>(count, n, A, lda, ipiv, info);
 }
 
 // ---- triangular product, inverse, SPD inverse ------------------------------

@@ -28,6 +28,8 @@ constexpr int kCholLeaf = 64;       // potf2 leaf: n <= kCholLeaf
 constexpr int kTrsmLeaf = 64;       // triangular solve leaf: triangle <= kTrsmLeaf
 constexpr int kLuLeaf = 32;         // getf2 panel width
 constexpr int kPanelMaxWG = 256;    // cooperative panel: at most one workgroup per CU
+constexpr int kBatchMaxSpd = 512;   // batched Cholesky: largest matrix (one workgroup per matrix)
+constexpr int kBatchMaxGe = 256;    // batched LU: largest matrix
 constexpr int kPanelRows = 512;     // panel rows per workgroup (two per thread)
 constexpr int kRecWords = 72;       // 64-bit words per panel exchange record
 constexpr int kRecSlots = kPanelMaxWG + 1;   // per step: one per workgroup, one for row d
@@ -187,6 +189,12 @@ void trmm(Ctx &c, char side, char uplo, char trans, char diag, long long m, long
 void trtri_rec(Ctx &c, char uplo, char diag, long long n, double *A, long long lda);
 void lauum_rec(Ctx &c, char uplo, long long n, double *A, long long lda);
 void diag_zero(Ctx &c, long long n, const double *A, long long lda);
+// Batched factorizations (batched.hip): one workgroup per matrix; the per-matrix
+// arrays (n, A, lda, ipiv, info) are device arrays of `count` entries.
+template <typename T>
+void potrf_batched(Ctx &c, bool upper, int count, const int *n, T *const *A, const int *lda, int *info);
+template <typename T>
+void getrf_batched(Ctx &c, int count, const int *n, T *const *A, const int *lda, int *const *ipiv, int *info);
 void trti2_leaf(Ctx &c, bool lower, bool unit, int t, double *A, long long lda);
 
 // Mixed precision helpers.
@@ -200,7 +208,7 @@ int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const 
                 double *berr);
 
 // Split rule: halves are multiples of kSplitQuantum where possible.
-inline long long split_size(long long n, long long quantum = kSplitQuantum) {
+__host__ __device__ inline long long split_size(long long n, long long quantum = kSplitQuantum) {
     if (n >= 2 * quantum) {
         long long n1 = ((n / 2 + quantum / 2) / quantum) * quantum;
         if (n1 < quantum) n1 = quantum;

@@ -7,6 +7,7 @@
 // paragraph on the crossover size; Sec. 4). Here the crossover is set by
 // on-chip capacity: a 64×64 FP64 diagonal block fits in one workgroup's LDS.
 #include "common.hpp"
+#include "wg.hpp"
 
 #include <climits>
 #include <utility>
@@ -21,158 +22,17 @@ namespace rl {
 // failing global column off+k+1 is recorded in status->info, the block is
 // written back as it stands (columns before k final, column k holding its
 // updated pivot) and every later kernel of the call sees info != 0 and
-// returns at once.
-//
-// The 64 columns are taken 16 at a time, right-looking: one wave factors the
-// 16-column panel (lane = row, the panel's 16 entries of the row in
-// registers, the 16 steps unrolled so every register index is fixed), then
-// all four waves subtract the panel's contribution from the trailing lower
-// triangle on the FP64 matrix cores. A step subtracts (a_rk / a_kk)·a_jk
-// from a_rj, which equals l_rk·l_jk and keeps the square root and the column
-// scaling off the step-to-step dependency chain; the panel's columns are
-// scaled to l_rk = a_rk / sqrt(a_kk) by all waves once the panel is done.
+// returns at once. The factorization itself is potf2_block (wg.hpp).
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T lane_bcast(T x, int l);
-template <>
-__device__ __forceinline__ double lane_bcast<double>(double x, int l) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
-    return __hiloint2double(hi, lo);
-}
-template <>
-__device__ __forceinline__ float lane_bcast<float>(float x, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
-}
-
-// C(16×16 tile at rows i0, columns j0) -= P(i0.., 16 columns from c0)·P(j0.., same)ᵀ
-// on the matrix cores; S is row-major with row stride 65.
-template <typename T>
-__device__ __forceinline__ void potf2_tile_update(T (*S)[65], int i0, int j0, int c0, int lane);
-template <>
-__device__ __forceinline__ void potf2_tile_update<double>(double (*S)[65], int i0, int j0, int c0, int lane) {
-    d4 acc = {0, 0, 0, 0};
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-        const int c = c0 + 4 * kk + (lane >> 4);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S[i0 + (lane & 15)][c], S[j0 + (lane & 15)][c], acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) S[i0 + (lane >> 4) + 4 * v][j0 + (lane & 15)] -= acc[v];
-}
-template <>
-__device__ __forceinline__ void potf2_tile_update<float>(float (*S)[65], int i0, int j0, int c0, int lane) {
-    f4 acc = {0, 0, 0, 0};
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-        const int c = c0 + 4 * kk + (lane >> 4);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(S[i0 + (lane & 15)][c], S[j0 + (lane & 15)][c], acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) S[i0 + 4 * (lane >> 4) + v][j0 + (lane & 15)] -= acc[v];
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void potf2_k(int n, T *__restrict__ A, long long lda, int upper,
                                                long long off, DevStatus *st) {
     if (st->info) return;
-    __shared__ T S[64][65];
-    __shared__ T cb[2][16];
-    __shared__ T dd[16];   // pivots a_kk of the current panel
-    __shared__ int fail_s;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ Potf2Lds<T> L;
     // element (i, j) of the lower factor lives at A[i + j*lda] ('L') or A[j + i*lda] ('U')
     const long long si = upper ? lda : 1, sj = upper ? 1 : lda;
-    {
-        T v[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int i = lane, j = wave + 4 * u;
-            v[u] = A[min(i, n - 1) * si + min(j, n - 1) * sj];
-        }
-        asm volatile("" ::: "memory");
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int i = lane, j = wave + 4 * u;
-            // lower triangle; rows and columns past n are the identity
-            S[i][j] = (i < n && j < n) ? (j <= i ? v[u] : T(0)) : (i == j ? T(1) : T(0));
-        }
-    }
-    if (tid == 0) fail_s = 0;
-    __syncthreads();
-    const int nb = (n + 15) / 16;
-    for (int J = 0; J < nb; ++J) {
-        if (wave == 0) {
-            const int r = lane;
-            T x[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) x[q] = S[r][16 * J + q];
-            int fail = 0;
-#pragma unroll
-            for (int kk = 0; kk < 16; ++kk) {
-                const int k = 16 * J + kk;
-                if (fail == 0 && k < n) {
-                    if ((r >> 4) == J) cb[kk & 1][r & 15] = x[kk];
-                    const T d = lane_bcast(x[kk], k);
-                    if (!(d > T(0))) {
-                        fail = k + 1;
-                    } else {
-                        // column kk of the panel's diagonal rows, as broadcasts
-                        T cv[16];
-#pragma unroll
-                        for (int q = kk + 1; q < 16; ++q) cv[q] = cb[kk & 1][q];
-                        const T t = x[kk] * (T(1) / d);
-                        S[r][k] = x[kk];   // a_rk; scaled by 1/sqrt(a_kk) after the panel
-                        if (r == 0) dd[kk] = d;
-#pragma unroll
-                        for (int q = kk + 1; q < 16; ++q) x[q] -= t * cv[q];
-                    }
-                }
-            }
-            if (fail) {
-                // the panel's columns from the failing one on, as they stand
-                const int k = fail - 1;
-#pragma unroll
-                for (int q = 0; q < 16; ++q)
-                    if (16 * J + q >= k && r >= 16 * J + q) S[r][16 * J + q] = x[q];
-                if (r == 0) fail_s = fail;
-            }
-        }
-        __syncthreads();
-        // l_rc = a_rc / sqrt(a_cc) for the panel's finished columns
-        {
-            const int fk = fail_s ? fail_s - 1 : n;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int r = lane, c = 16 * J + wave + 4 * u;
-                if (c < fk && r >= c) {
-                    const T lkk = sqrt(dd[c - 16 * J]);
-                    S[r][c] = (r == c) ? lkk : S[r][c] / lkk;
-                }
-            }
-        }
-        __syncthreads();
-        if (fail_s) break;
-        // trailing lower triangle: tiles (I, Jt) with J < Jt <= I < nb
-        const int m = nb - 1 - J;   // trailing tile rows
-        const int ntiles = m * (m + 1) / 2;
-        for (int tt = wave; tt < ntiles; tt += 4) {
-            // tt -> (I, Jt) in the trailing triangle
-            int I = 0, acc = 0;
-            while (acc + I + 1 <= tt) { acc += I + 1; ++I; }
-            const int Jt = tt - acc;
-            potf2_tile_update<T>(S, 16 * (J + 1 + I), 16 * (J + 1 + Jt), 16 * J, lane);
-        }
-        __syncthreads();
-    }
-    const int fail = fail_s;
-    if (fail && tid == 0) atomicCAS(&st->info, 0, (int)(off + fail));
-    // write back the lower triangle
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const int i = lane, j = wave + 4 * u;
-        if (i < n && j <= i) A[i * si + j * sj] = S[i][j];
-    }
+    const int fail = potf2_block(n, A, si, sj, L);
+    if (fail && threadIdx.x == 0) atomicCAS(&st->info, 0, (int)(off + fail));
 }
 
 template <typename T>
@@ -238,69 +98,6 @@ __device__ __forceinline__ void pubw(unsigned long long *p, unsigned long long v
 }
 __device__ __forceinline__ unsigned long long subw(const unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// ---- wave-level reductions (DPP, no LDS crossbar) --------------------------
-template <int CTRL>
-__device__ __forceinline__ unsigned dpp_u32(unsigned x) {
-    return (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, 0xF, 0xF, false);
-}
-__device__ __forceinline__ unsigned rlane(unsigned x, int l) { return (unsigned)__builtin_amdgcn_readlane((int)x, l); }
-// Maximum / minimum over the wave, in every lane: quad swaps, then the
-// half-row and row mirrors give each 16-lane row its extreme; the 4 rows are
-// combined from one lane of each.
-__device__ __forceinline__ unsigned wave_max_u32(unsigned x) {
-    x = max(x, dpp_u32<0xB1>(x));   // quad_perm [1,0,3,2]
-    x = max(x, dpp_u32<0x4E>(x));   // quad_perm [2,3,0,1]
-    x = max(x, dpp_u32<0x141>(x));  // row_half_mirror
-    x = max(x, dpp_u32<0x140>(x));  // row_mirror
-    return max(max(rlane(x, 0), rlane(x, 16)), max(rlane(x, 32), rlane(x, 48)));
-}
-__device__ __forceinline__ unsigned wave_min_u32(unsigned x) {
-    x = min(x, dpp_u32<0xB1>(x));
-    x = min(x, dpp_u32<0x4E>(x));
-    x = min(x, dpp_u32<0x141>(x));
-    x = min(x, dpp_u32<0x140>(x));
-    return min(min(rlane(x, 0), rlane(x, 16)), min(rlane(x, 32), rlane(x, 48)));
-}
-// Candidate key: 0 for "no candidate" (retired, out of range or NaN), else
-// the bit pattern of the non-negative magnitude plus one, so keys order like
-// magnitudes and key 1 is an exact zero.
-__device__ __forceinline__ unsigned long long cand_key(double mag, bool valid) {
-    return (valid && mag == mag) ? (unsigned long long)__double_as_longlong(mag) + 1ull : 0ull;
-}
-// (key, position) order of the pivot search: larger key, then lower position.
-__device__ __forceinline__ bool cand_wins(unsigned long long k2, unsigned p2, unsigned long long k1, unsigned p1) {
-    return k2 > k1 || (k2 == k1 && p2 < p1);
-}
-// The wave's winning lane (-1 if no lane has a candidate) with its key and
-// position. Positions are only compared when keys tie exactly. Uniform
-// control flow throughout (readlane). The 64-bit maximum takes the high
-// halves first; a unique largest high half (the usual case for data that are
-// not exact ties) already names the winner, else the low halves of the lanes
-// that share it decide.
-__device__ __forceinline__ int wave_winner(unsigned long long key, unsigned pos, unsigned long long &wk, unsigned &wp) {
-    const unsigned khi = (unsigned)(key >> 32);
-    const unsigned hi = wave_max_u32(khi);
-    const unsigned long long bh = __ballot(khi == hi);
-    if (__builtin_popcountll(bh) == 1) {
-        // hi exceeds every other lane's high half, so it is nonzero: a candidate
-        const int wl = (int)__builtin_ctzll(bh);
-        wk = ((unsigned long long)hi << 32) | rlane((unsigned)key, wl);
-        wp = rlane(pos, wl);
-        return wl;
-    }
-    wk = ((unsigned long long)hi << 32) | wave_max_u32(khi == hi ? (unsigned)key : 0u);
-    const bool mine = key == wk && key != 0;
-    const unsigned long long ball = __ballot(mine);
-    if (ball == 0) { wp = 0xFFFFFFFFu; return -1; }
-    if (__builtin_popcountll(ball) == 1) {
-        const int wl = (int)__builtin_ctzll(ball);
-        wp = rlane(pos, wl);
-        return wl;
-    }
-    wp = wave_min_u32(mine ? pos : 0xFFFFFFFFu);
-    return (int)__builtin_ctzll(__ballot(mine && pos == wp));
 }
 
 // 32-bit chunks of a value, for epoch-tagged words

@@ -11,157 +11,11 @@
 // B[e*se + r*sr]. Left-side solves use se = 1 (columns of B), right-side
 // solves use sr = 1 (rows of B) with N = op(T)ᵀ.
 #include "common.hpp"
+#include "wg.hpp"
 
 #include <type_traits>
 
 namespace rl {
-
-// ---------------------------------------------------------------------------
-// Matrix-core leaf: a workgroup solves N·x = b for 64 vectors (16 per wave),
-// triangle t <= 64 in LDS, blocked by 16: block I of x is
-//     x_I = N_II⁻¹ (b_I - Σ_{J before I} N_IJ·x_J),
-// the sum on the matrix cores (16×16×4 steps, vectors as columns), the 16×16
-// diagonal solve by substitution with four lanes per vector. The reciprocals
-// of the diagonal are formed once after the triangle is staged, and rows
-// beyond t are padded with the identity, so the substitution is straight-line
-// code with a multiply, a quad broadcast and an FMA on its dependency chain
-// per step. Each wave works on its own 16 vectors, so waves never wait for
-// each other after the triangle is staged.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double lane_bcast(double x, int l) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ float lane_bcast(float x, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
-}
-
-// The value of lane S of each group of four lanes, in all four (DPP quad_perm).
-template <int S>
-__device__ __forceinline__ float quad_bcast(float x) {
-    constexpr int ctrl = S | (S << 2) | (S << 4) | (S << 6);
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xF, 0xF, false));
-}
-template <int S>
-__device__ __forceinline__ double quad_bcast(double x) {
-    constexpr int ctrl = S | (S << 2) | (S << 4) | (S << 6);
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), ctrl, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), ctrl, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-// quad_bcast with the source lane chosen at run time; fully unrolled callers
-// pass a constant, so the switch folds away.
-template <typename T>
-__device__ __forceinline__ T quad_bcast_sel(T x, int s) {
-    switch (s & 3) {
-    case 0: return quad_bcast<0>(x);
-    case 1: return quad_bcast<1>(x);
-    case 2: return quad_bcast<2>(x);
-    default: return quad_bcast<3>(x);
-    }
-}
-
-template <typename TW>
-struct LeafMfma;
-template <>
-struct LeafMfma<double> {
-    typedef d4 acc_t;
-    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
-};
-template <>
-struct LeafMfma<float> {
-    typedef f4 acc_t;
-    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
-};
-
-// One wave solves N·x = b for its 16 vectors, N the 64×64 triangle in Nsh
-// (rows and columns beyond t padded with the identity), x in the wave's X
-// (64 rows × 16 vectors): 16-row blocks in the order of the solve, each first
-// updated on the matrix cores with the blocks already solved, then finished
-// by substitution.
-template <typename TW, bool LOWER>
-__device__ __forceinline__ void solve64(TW (*Nsh)[65], TW (*X)[17], int t, int unit, int lane) {
-    typedef LeafMfma<TW> Op;
-    typedef typename Op::acc_t acc_t;
-    // reciprocal of diagonal element `lane`, formed in every wave off the
-    // substitution's dependency chain (read back with readlane)
-    TW rdl = (unit || lane >= t) ? TW(1) : TW(1) / Nsh[lane][lane];
-    asm volatile("" : "+v"(rdl));
-
-    const int nblk = (t + 15) / 16;
-    for (int s = 0; s < nblk; ++s) {
-        const int I = LOWER ? s : nblk - 1 - s;
-        // X_I -= Σ N_IJ·X_J over the blocks already solved
-        if (s > 0) {
-            acc_t acc = acc_t{0, 0, 0, 0};
-            const int J0 = LOWER ? 0 : I + 1, J1 = LOWER ? I : nblk;
-            for (int J = J0; J < J1; ++J) {
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const int k = 16 * J + 4 * kk + (lane >> 4);
-                    acc = Op::mma(Nsh[16 * I + (lane & 15)][k], X[k][lane & 15], acc);
-                }
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) X[16 * I + Op::row(lane, v)][lane & 15] -= acc[v];
-            __builtin_amdgcn_wave_barrier();
-        }
-        // diagonal 16×16 block: four lanes per vector (lane = 4·vector + r,
-        // rows 4r..4r+3 of the block), so all 64 lanes work and each step's
-        // x_j reaches the vector's other lanes by a quad broadcast; the
-        // block's reciprocals come from readlane in uniform control flow and
-        // the next column's entries are read ahead of the current updates
-        TW rds[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) rds[j] = lane_bcast(rdl, 16 * I + j);
-        {
-            const int v = lane >> 2, r4 = lane & 3;
-            TW x[4], nc[4], nn[4];
-#pragma unroll
-            for (int t4 = 0; t4 < 4; ++t4) x[t4] = X[16 * I + 4 * r4 + t4][v];
-#pragma unroll
-            for (int t4 = 0; t4 < 4; ++t4) nc[t4] = Nsh[16 * I + 4 * r4 + t4][16 * I + (LOWER ? 0 : 15)];
-#pragma unroll
-            for (int s2 = 0; s2 < 16; ++s2) {
-                const int j = LOWER ? s2 : 15 - s2, jb = j >> 2, jj = j & 3;
-                if (s2 + 1 < 16) {
-#pragma unroll
-                    for (int t4 = 0; t4 < 4; ++t4) nn[t4] = Nsh[16 * I + 4 * r4 + t4][16 * I + (LOWER ? j + 1 : j - 1)];
-                }
-                // the column read one step ago is complete here; the empty asm
-                // also keeps the compiler from turning the selects below into
-                // branches around the loads
-#pragma unroll
-                for (int t4 = 0; t4 < 4; ++t4) asm volatile("" : "+v"(nc[t4]));
-                const TW xs = x[jj] * rds[j];
-                const TW xb = quad_bcast_sel(xs, jb);
-#pragma unroll
-                for (int t4 = 0; t4 < 4; ++t4) {
-                    const TW f = x[t4] - nc[t4] * xb;
-                    // rows after j in the order of the solve take the update,
-                    // row j takes its solved value, the others stay
-                    const bool after = LOWER ? (t4 > jj ? r4 >= jb : r4 > jb) : (t4 < jj ? r4 <= jb : r4 < jb);
-                    const TW keep = (t4 == jj && r4 == jb) ? xs : x[t4];
-                    x[t4] = after ? f : keep;
-                }
-#pragma unroll
-                for (int t4 = 0; t4 < 4; ++t4) nc[t4] = nn[t4];
-            }
-#pragma unroll
-            for (int t4 = 0; t4 < 4; ++t4) X[16 * I + 4 * r4 + t4][v] = x[t4];
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-
-}
 
 // INV = true: the right-hand sides are the columns of the identity (not read
 // from B) and only the triangle of the solution is written back, so a single
