@@ -21,7 +21,9 @@ the dominant kernel, the FP64 matrix-core GEMM on 128×128 tiles.
 ``spd_inverse`` times dpotri (dtrtri + dlauum of the Cholesky factor) at
 n = 8192 (``--inv-n``); ``variants`` times dpotrf with uplo = 'U' and the
 single-precision spotrf / sgetrf at the benchmark size (``--no-variants``
-skips them).
+skips them); ``batched`` times one call of each batched routine over 20000
+matrices of uneven sizes (``--batch-count``; SPD n in [8, 512], general n in
+[8, 256]) in FP64 and FP32.
 
 Prints ONE JSON line. ``--gpus N`` with N > 1 exits: the library runs on one GPU.
 ``--copy-calib MB`` only runs a plain device copy of that size 20 times (the
@@ -64,6 +66,8 @@ def parse():
     p.add_argument("--target-n", type=int, default=32768,
                    help="also time one dpotrf + dgetrf at this size (0: skip)")
     p.add_argument("--no-variants", action="store_true", help="skip the uplo = 'U' and FP32 timings")
+    p.add_argument("--batch-count", type=int, default=20000,
+                   help="matrices per batched routine (SPD n in [8, 512], general n in [8, 256]); 0 skips")
     p.add_argument("--inv-n", type=int, default=8192,
                    help="also time the SPD inverse (dtrtri + dlauum of a dpotrf factor) at this size (0: skip)")
     return p.parse_args()
@@ -276,6 +280,99 @@ def variants(n: int, stream, reps: int = 3):
     return out
 
 
+def batched(count: int, stream, reps: int = 3, seed: int = 4):
+    """The batched workload of uneven sizes: ``count`` SPD matrices with n
+    uniform in [8, 512] (A = B·Bᵀ + n·I, B ~ U[-1, 1]) and ``count`` general
+    matrices with n uniform in [8, 256] (U[-1, 1]), all sizes from one seed,
+    each routine one call over its whole batch, in FP64 and FP32 (the FP64
+    inputs rounded). Median of ``reps`` calls after an untimed one, the inputs
+    restored before each. The bound is the per-matrix roofline summed over the
+    batch: max(flops / matrix peak, bytes / HBM bandwidth) with n³/3 flops and
+    8n² B (Cholesky), 2n³/3 flops and 16n² B (LU), halved bytes in FP32."""
+    import numpy as np
+    import torch
+
+    import paper_1602_06763_amd as rl
+
+    g = np.random.default_rng(seed)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    out = {"count_spd": count, "count_general": count, "n_spd": "U{8..512}", "n_general": "U{8..256}"}
+
+    def build(ns, spd):
+        offs = np.concatenate([[0], np.cumsum(ns.astype(np.int64) ** 2)])
+        buf = torch.empty(int(offs[-1]), dtype=torch.float64, device="cuda")
+        gen_t = torch.Generator(device="cuda")
+        gen_t.manual_seed(seed + (1 if spd else 2))
+        if spd:
+            for n in np.unique(ns):
+                idx = np.nonzero(ns == n)[0]
+                B = torch.rand((len(idx), int(n), int(n)), dtype=torch.float64, device="cuda", generator=gen_t) * 2 - 1
+                A = torch.bmm(B, B.transpose(1, 2).contiguous())
+                A.diagonal(dim1=1, dim2=2).add_(float(n))
+                for q, i in enumerate(idx):
+                    buf[int(offs[i]):int(offs[i + 1])].copy_(A[q].reshape(-1))
+                del B, A
+        else:
+            buf.uniform_(-1.0, 1.0, generator=gen_t)
+        return buf, offs
+
+    def run(name, ns, buf, offs, call, flops, nbytes, peak, ipiv=None):
+        esz = buf.element_size()
+        ptrs = torch.tensor(buf.data_ptr() + esz * offs[:-1], dtype=torch.int64, device="cuda")
+        nv = torch.tensor(ns, dtype=torch.int32, device="cuda")
+        info = torch.zeros(len(ns), dtype=torch.int32, device="cuda")
+        src = buf.clone()
+        ts = []
+        for r in range(reps + 1):
+            buf.copy_(src)
+            torch.cuda.synchronize()
+            e0, e1 = ev(), ev()
+            e0.record(stream)
+            st = call(nv, ptrs, info)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            assert st == 0 and int(info.abs().max()) == 0
+            if r:
+                ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        n = ns.astype(np.float64)
+        fl = float(np.sum(flops(n)))
+        bound_s = float(np.sum(np.maximum(flops(n) / (peak * 1e12), nbytes(n) / (PEAK_HBM * 1e9))))
+        out[name] = {"ms": round(ms, 3), "matrices_per_s": round(len(ns) / (ms * 1e-3), 1),
+                     "tflops": round(fl / (ms * 1e-3) / 1e12, 3), "roofline_bound_ms": round(bound_s * 1e3, 3),
+                     "frac_of_bound": round(bound_s * 1e3 / ms, 4)}
+        del src
+        return ms
+
+    ns_spd = g.integers(8, 513, size=count)
+    ns_ge = g.integers(8, 257, size=count)
+    chol_f, lu_f = (lambda n: n ** 3 / 3.0), (lambda n: 2.0 * n ** 3 / 3.0)
+    buf, offs = build(ns_spd, True)
+    run("dpotrf", ns_spd, buf, offs, lambda nv, p, info: rl.potrf_batched("L", count, nv, p, nv, info),
+        chol_f, lambda n: 8.0 * n * n, PEAK_FP64)
+    sb = buf.float()
+    del buf
+    torch.cuda.empty_cache()
+    run("spotrf", ns_spd, sb, offs, lambda nv, p, info: rl.potrf_batched("L", count, nv, p, nv, info, single=True),
+        chol_f, lambda n: 4.0 * n * n, PEAK_FP32)
+    del sb
+    torch.cuda.empty_cache()
+    poffs = np.concatenate([[0], np.cumsum(ns_ge.astype(np.int64))])
+    piv = torch.zeros(int(poffs[-1]), dtype=torch.int32, device="cuda")
+    pp = torch.tensor(piv.data_ptr() + 4 * poffs[:-1], dtype=torch.int64, device="cuda")
+    buf, offs = build(ns_ge, False)
+    run("dgetrf", ns_ge, buf, offs, lambda nv, p, info: rl.getrf_batched(count, nv, p, nv, pp, info),
+        lu_f, lambda n: 16.0 * n * n, PEAK_FP64)
+    sb = buf.float()
+    del buf
+    torch.cuda.empty_cache()
+    run("sgetrf", ns_ge, sb, offs, lambda nv, p, info: rl.getrf_batched(count, nv, p, nv, pp, info, single=True),
+        lu_f, lambda n: 8.0 * n * n, PEAK_FP32)
+    del sb, piv
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_calibration(mb: float):
     import torch
 
@@ -466,6 +563,8 @@ def main():
         out["spd_inverse"] = spd_inverse(args.inv_n, stream)
     if not args.no_variants:
         out["variants"] = variants(n, stream)
+    if args.batch_count > 0:
+        out["batched"] = batched(args.batch_count, stream)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_n1)
     print(json.dumps(out))

@@ -7,8 +7,8 @@
 // Sec. 5 keeps LAPACK's statement of xpotrf and xgetrf): Cholesky splits the
 // matrix, LU splits the columns, and every off-leaf operation is a triangular
 // solve or a product on the matrix cores. A matrix of at most 512 rows (SPD)
-// or 256 rows (LU) stays in the L2 cache while its workgroup works on it, so
-// the workgroup-level operations read their operands straight from memory:
+// or 256 rows (LU) stays in the L2 cache while its workgroup works on it; the
+// workgroup-level operations are:
 //   - potf2 leaf: the unblocked Cholesky of a <= 64 block in LDS (potf2_block);
 //   - LU leaf: a <= 32-column panel of all rows below the diagonal in LDS, one
 //     row per thread, partial pivoting with the pivot rule of the single-matrix
@@ -18,16 +18,15 @@
 //     reaches every column once, in order, as in LAPACK's dgetrf);
 //   - triangular solves by 64-row blocks of the triangle (solve64 on 16 vectors
 //     per wave) with the remaining rows updated on the matrix cores;
-//   - products C -= A·B by 32×32 blocks per wave on the matrix cores, the lower
-//     triangle only for the Cholesky update.
-// The recursion depth is a template parameter, so the device code has no
-// unbounded call stack.
+//   - products C -= A·B by 64×64 tiles per workgroup on the matrix cores, K
+//     staged through LDS, the lower triangle only for the Cholesky update.
+// The recursion runs from an explicit stack of frames in LDS, so every
+// operation is inlined once and the kernel makes no calls.
 #include "common.hpp"
 #include "wg.hpp"
 
 namespace rl {
 
-constexpr int kBatchDepth = 6;   // deeper than any split chain of n <= 512
 
 // Element (i, j) of a strided matrix view at p[i*r + j*c].
 template <typename T>
@@ -53,10 +52,17 @@ struct PanelLdsB {
 };
 
 template <typename T>
+struct GemmLdsB {
+    T As[2][32][65];   // [buffer][k][row]
+    T Bs[2][32][65];   // [buffer][k][column]
+};
+
+template <typename T>
 union BatchLds {
     Potf2Lds<T> p2;
     TrsmLds<T> ts;
     PanelLdsB<T> pl;
+    GemmLdsB<T> gm;
 };
 
 extern __shared__ __attribute__((aligned(16))) unsigned char batch_smem[];
@@ -67,56 +73,87 @@ __device__ __forceinline__ BatchLds<T> &blds() {
 }
 
 // C -= A·B by one workgroup on the matrix cores: C is M×N, A is M×K, B is
-// K×N. Each wave takes 32×32 blocks of C in turn (four 16×16 accumulators,
-// K in steps of 16); TRI computes and writes only the lower triangle of C.
-// Operands are read with clamped indices (always inside the views) and
-// zeroed outside them.
+// K×N. The workgroup takes 64×64 tiles of C in turn (each wave a 32×32
+// quarter, four 16×16 accumulators); K goes in chunks of 32 staged in LDS,
+// double buffered, the next chunk's loads in flight while the current one is
+// multiplied. Threads run along whichever index of an operand has unit
+// stride, so the loads are contiguous for every view the recursion passes.
+// TRI computes and writes only the lower triangle of C. Operands are read
+// with clamped indices (always inside the views) and zeroed outside them.
 template <typename T, bool TRI>
-__device__ __attribute__((noinline)) void wg_gemm(int M, int N, int K, WgMat<const T> A, WgMat<const T> B,
+__device__ __forceinline__ void wg_gemm(int M, int N, int K, WgMat<const T> A, WgMat<const T> B,
                                                   WgMat<T> C) {
     typedef LeafMfma<T> Op;
     typedef typename Op::acc_t acc_t;
     if (M <= 0 || N <= 0 || K <= 0) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    GemmLdsB<T> &L = blds<T>().gm;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int bm = (M + 31) / 32, bn = (N + 31) / 32;
-    for (int blk = wave; blk < bm * bn; blk += 4) {
-        const int bi = blk % bm, bj = blk / bm;
-        if (TRI && bi < bj) continue;
-        const int i0 = 32 * bi, j0 = 32 * bj;
+    const int wi = 32 * (wave & 1), wj = 32 * (wave >> 1);   // this wave's quarter of the tile
+    const bool a_rows = A.r == 1, b_cols = B.c == 1;
+    const int tm = (M + 63) / 64, tn = (N + 63) / 64;
+    for (int tile = 0; tile < tm * tn; ++tile) {
+        const int bi = tile % tm, bj = tile / tm;
+        if (TRI && bi < bj) continue;   // uniform across the workgroup
+        const int i0 = 64 * bi, j0 = 64 * bj;
+        T ra[8], rb[8];
+        auto fetch = [&](int k0) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = tid + 256 * u;
+                const int ia = a_rows ? (idx & 63) : (idx >> 5), ka = a_rows ? (idx >> 6) : (idx & 31);
+                const int jb = b_cols ? (idx & 63) : (idx >> 5), kb = b_cols ? (idx >> 6) : (idx & 31);
+                const int gi = i0 + ia, gka = k0 + ka, gj = j0 + jb, gkb = k0 + kb;
+                const T av = A(min(gi, M - 1), min(gka, K - 1)), bv = B(min(gkb, K - 1), min(gj, N - 1));
+                ra[u] = (gi < M && gka < K) ? av : T(0);
+                rb[u] = (gj < N && gkb < K) ? bv : T(0);
+            }
+        };
+        auto stage = [&](int buf) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = tid + 256 * u;
+                const int ia = a_rows ? (idx & 63) : (idx >> 5), ka = a_rows ? (idx >> 6) : (idx & 31);
+                const int jb = b_cols ? (idx & 63) : (idx >> 5), kb = b_cols ? (idx >> 6) : (idx & 31);
+                L.As[buf][ka][ia] = ra[u];
+                L.Bs[buf][kb][jb] = rb[u];
+            }
+        };
         acc_t acc[2][2];
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int t = 0; t < 2; ++t) acc[s][t] = acc_t{0, 0, 0, 0};
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            T a[4][2], b[4][2];
+        fetch(0);
+        int buf = 0;
+        for (int k0 = 0; k0 < K; k0 += 32) {
+            stage(buf);
+            __syncthreads();
+            if (k0 + 32 < K) fetch(k0 + 32);
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int k = k0 + 4 * kk + lk;
-                const int kc = min(k, K - 1);
+            for (int kk = 0; kk < 8; ++kk) {
+                const int k = 4 * kk + lk;
+                T a[2], b[2];
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
-                    const int i = i0 + 16 * s + lr, j = j0 + 16 * s + lr;
-                    const T av = A(min(i, M - 1), kc), bv = B(kc, min(j, N - 1));
-                    a[kk][s] = (i < M && k < K) ? av : T(0);
-                    b[kk][s] = (j < N && k < K) ? bv : T(0);
+                    a[s] = L.As[buf][k][wi + 16 * s + lr];
+                    b[s] = L.Bs[buf][k][wj + 16 * s + lr];
                 }
-            }
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
                 for (int s = 0; s < 2; ++s)
 #pragma unroll
-                    for (int t = 0; t < 2; ++t) acc[s][t] = Op::mma(a[kk][s], b[kk][t], acc[s][t]);
+                    for (int t = 0; t < 2; ++t) acc[s][t] = Op::mma(a[s], b[t], acc[s][t]);
+            }
+            buf ^= 1;
         }
+        __syncthreads();   // every wave is done with both buffers before the next tile stages
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int t = 0; t < 2; ++t)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int i = i0 + 16 * s + Op::row(lane, v), j = j0 + 16 * t + lr;
+                    const int i = i0 + wi + 16 * s + Op::row(lane, v), j = j0 + wj + 16 * t + lr;
                     if (i < M && j < N && (!TRI || i >= j)) C(i, j) -= acc[s][t][v];
                 }
     }
@@ -129,7 +166,7 @@ __device__ __attribute__((noinline)) void wg_gemm(int M, int N, int K, WgMat<con
 // beyond the triangle) and solved for 64 vectors at a time (16 per wave),
 // then the rows below it are updated on the matrix cores.
 template <typename T>
-__device__ __attribute__((noinline)) void wg_trsm(int t, int nvec, int unit, WgMat<const T> N, WgMat<T> X) {
+__device__ __forceinline__ void wg_trsm(int t, int nvec, int unit, WgMat<const T> N, WgMat<T> X) {
     if (t <= 0 || nvec <= 0) return;
     TrsmLds<T> &L = blds<T>().ts;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -168,30 +205,52 @@ __device__ __attribute__((noinline)) void wg_trsm(int t, int nvec, int unit, WgM
     }
 }
 
-// Recursive Cholesky of the n×n block whose lower-factor element (i, j) is
+// Frames of the recursion, run by an explicit stack that every thread keeps
+// identically in LDS: kind 0 = factor (off, n), kind 1 = the update between
+// the halves (off, n, n1). A call pushes its right half, the update and its
+// left half, so the left half is taken first, as in the recursive call.
+struct BFrame {
+    int kind, off, n, n1;
+};
+constexpr int kBatchStack = 3 * 8 + 1;   // three frames per level, 8 levels cover n <= 512
+
+// Recursive Cholesky of the n×n matrix whose lower-factor element (i, j) is
 // A[i*si + j*sj]: A11 = L11·L11ᵀ; A21 := A21·L11⁻ᵀ; A22 -= A21·A21ᵀ; A22 =
-// L22·L22ᵀ. Returns 0 or the first failing column (1-based, as potf2_block).
-template <typename T, int D>
-__device__ __attribute__((noinline)) int potrf_b(int n, T *A, long long si, long long sj) {
-    if (n <= kCholLeaf) {
-        const int f = potf2_block(n, A, si, sj, blds<T>().p2);
-        __syncthreads();
-        return f;
+// L22·L22ᵀ. Returns 0 or the first failing column (1-based, as potf2_block);
+// nothing after a failing leaf runs.
+template <typename T>
+__device__ __forceinline__ int potrf_b(int n, T *A, long long si, long long sj, BFrame *stk) {
+    int sp = 0;
+    if (threadIdx.x == 0) stk[0] = BFrame{0, 0, n, 0};
+    sp = 1;
+    __syncthreads();
+    while (sp > 0) {
+        const BFrame f = stk[--sp];
+        __syncthreads();   // every thread has read the frame before it is overwritten
+        T *Ao = A + f.off * si + f.off * sj;
+        if (f.kind == 0 && f.n <= kCholLeaf) {
+            const int r = potf2_block(f.n, Ao, si, sj, blds<T>().p2);
+            __syncthreads();
+            if (r) return f.off + r;
+        } else if (f.kind == 0) {
+            const int n1 = (int)split_size(f.n);
+            if (threadIdx.x == 0) {
+                stk[sp] = BFrame{0, f.off + n1, f.n - n1, 0};
+                stk[sp + 1] = BFrame{1, f.off, f.n, n1};
+                stk[sp + 2] = BFrame{0, f.off, n1, 0};
+            }
+            sp += 3;
+            __syncthreads();
+        } else {
+            const int n1 = f.n1, n2 = f.n - f.n1;
+            // the rows of A21 are the vectors of the solve with the triangle L11
+            wg_trsm<T>(n1, n2, 0, WgMat<const T>{Ao, si, sj}, WgMat<T>{Ao + n1 * si, sj, si});
+            wg_gemm<T, true>(n2, n2, n1, WgMat<const T>{Ao + n1 * si, si, sj},
+                             WgMat<const T>{Ao + n1 * si, sj, si}, WgMat<T>{Ao + n1 * si + n1 * sj, si, sj});
+            __syncthreads();
+        }
     }
-    if constexpr (D + 1 >= kBatchDepth) {
-        return -1;
-    } else {
-        const int n1 = (int)split_size(n), n2 = n - n1;
-        const int f = potrf_b<T, D + 1>(n1, A, si, sj);
-        if (f) return f;
-        // the rows of A21 are the vectors of the solve with the triangle L11
-        wg_trsm<T>(n1, n2, 0, WgMat<const T>{A, si, sj}, WgMat<T>{A + n1 * si, sj, si});
-        wg_gemm<T, true>(n2, n2, n1, WgMat<const T>{A + n1 * si, si, sj}, WgMat<const T>{A + n1 * si, sj, si},
-                         WgMat<T>{A + n1 * si + n1 * sj, si, sj});
-        __syncthreads();
-        const int f2 = potrf_b<T, D + 1>(n2, A + n1 * si + n1 * sj, si, sj);
-        return f2 > 0 ? n1 + f2 : f2;
-    }
+    return 0;
 }
 
 // LU panel of the columns c0..c0+w-1 (w <= 32) over the rows c0..n-1 of the
@@ -203,7 +262,7 @@ __device__ __attribute__((noinline)) int potrf_b(int n, T *A, long long si, long
 // interchanges are applied to every other column of the matrix. Returns the
 // first exactly zero pivot column (global, 1-based) or 0.
 template <typename T>
-__device__ __attribute__((noinline)) int wg_getf2(int n, T *A, long long lda, int c0, int w, int *ipiv) {
+__device__ __forceinline__ int wg_getf2(int n, T *A, long long lda, int c0, int w, int *ipiv) {
     PanelLdsB<T> &P = blds<T>().pl;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int mp = n - c0;   // panel rows, <= kBatchMaxGe
@@ -272,56 +331,77 @@ __device__ __attribute__((noinline)) int wg_getf2(int n, T *A, long long lda, in
     return zf;
 }
 
-// Recursive LU with partial pivoting of the columns c0..c0+w-1 of the n×n
-// matrix (rows c0..n-1): the left half, A12 := L11⁻¹·A12 (unit lower),
-// A22 -= A21·A12, the right half. Returns the first exactly zero pivot column
-// (global, 1-based) or 0; the factorization always completes.
-template <typename T, int D>
-__device__ __attribute__((noinline)) int getrf_b(int n, T *A, long long lda, int c0, int w, int *ipiv) {
-    if (w <= kLuLeaf) return wg_getf2<T>(n, A, lda, c0, w, ipiv);
-    if constexpr (D + 1 >= kBatchDepth) {
-        return -1;
-    } else {
-        const int w1 = (int)split_size(w), w2 = w - w1;
-        const int f1 = getrf_b<T, D + 1>(n, A, lda, c0, w1, ipiv);
-        wg_trsm<T>(w1, w2, 1, WgMat<const T>{A + c0 + c0 * lda, 1, lda}, WgMat<T>{A + c0 + (c0 + w1) * lda, 1, lda});
-        wg_gemm<T, false>(n - c0 - w1, w2, w1, WgMat<const T>{A + (c0 + w1) + c0 * lda, 1, lda},
-                          WgMat<const T>{A + c0 + (c0 + w1) * lda, 1, lda},
-                          WgMat<T>{A + (c0 + w1) + (c0 + w1) * lda, 1, lda});
+// Recursive LU with partial pivoting of the n×n matrix (columns split in
+// halves, rows from the diagonal down): the left half, A12 := L11⁻¹·A12
+// (unit lower), A22 -= A21·A12, the right half; frames as for the Cholesky
+// (off = first column, n = columns, n1 = left half). Returns the first exactly
+// zero pivot column (global, 1-based) or 0; the factorization always
+// completes.
+template <typename T>
+__device__ __forceinline__ int getrf_b(int n, T *A, long long lda, int *ipiv, BFrame *stk) {
+    int sp = 0, info = 0;
+    if (threadIdx.x == 0) stk[0] = BFrame{0, 0, n, 0};
+    sp = 1;
+    __syncthreads();
+    while (sp > 0) {
+        const BFrame f = stk[--sp];
         __syncthreads();
-        const int f2 = getrf_b<T, D + 1>(n, A, lda, c0 + w1, w2, ipiv);
-        return f1 ? f1 : f2;
+        const int c0 = f.off;
+        if (f.kind == 0 && f.n <= kLuLeaf) {
+            const int r = wg_getf2<T>(n, A, lda, c0, f.n, ipiv);
+            if (info == 0) info = r;
+        } else if (f.kind == 0) {
+            const int w1 = (int)split_size(f.n);
+            if (threadIdx.x == 0) {
+                stk[sp] = BFrame{0, c0 + w1, f.n - w1, 0};
+                stk[sp + 1] = BFrame{1, c0, f.n, w1};
+                stk[sp + 2] = BFrame{0, c0, w1, 0};
+            }
+            sp += 3;
+            __syncthreads();
+        } else {
+            const int w1 = f.n1, w2 = f.n - f.n1;
+            wg_trsm<T>(w1, w2, 1, WgMat<const T>{A + c0 + c0 * lda, 1, lda},
+                       WgMat<T>{A + c0 + (c0 + w1) * lda, 1, lda});
+            wg_gemm<T, false>(n - c0 - w1, w2, w1, WgMat<const T>{A + (c0 + w1) + c0 * lda, 1, lda},
+                              WgMat<const T>{A + c0 + (c0 + w1) * lda, 1, lda},
+                              WgMat<T>{A + (c0 + w1) + (c0 + w1) * lda, 1, lda});
+            __syncthreads();
+        }
     }
+    return info;
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void potrf_batched_k(int count, int upper, const int *__restrict__ nv,
+__global__ __launch_bounds__(256, 2) void potrf_batched_k(int count, int upper, const int *__restrict__ nv,
                                                       T *const *__restrict__ Av, const int *__restrict__ ldav,
                                                       int *__restrict__ infov) {
     const int b = blockIdx.x;
     if (b >= count) return;
+    __shared__ BFrame stk[kBatchStack];
     const int n = nv[b], lda = ldav[b];
     int info = 0;
     if (n < 0 || n > kBatchMaxSpd) info = -2;
     else if (lda < max(1, n)) info = -4;
     else if (n > 0) {
         const long long si = upper ? lda : 1, sj = upper ? 1 : lda;
-        info = potrf_b<T, 0>(n, Av[b], si, sj);
+        info = potrf_b<T>(n, Av[b], si, sj, stk);
     }
     if (threadIdx.x == 0) infov[b] = info;
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void getrf_batched_k(int count, const int *__restrict__ nv,
+__global__ __launch_bounds__(256, 2) void getrf_batched_k(int count, const int *__restrict__ nv,
                                                       T *const *__restrict__ Av, const int *__restrict__ ldav,
                                                       int *const *__restrict__ ipivv, int *__restrict__ infov) {
     const int b = blockIdx.x;
     if (b >= count) return;
+    __shared__ BFrame stk[kBatchStack];
     const int n = nv[b], lda = ldav[b];
     int info = 0;
     if (n < 0 || n > kBatchMaxGe) info = -2;
     else if (lda < max(1, n)) info = -4;
-    else if (n > 0) info = getrf_b<T, 0>(n, Av[b], lda, 0, n, ipivv[b]);
+    else if (n > 0) info = getrf_b<T>(n, Av[b], lda, ipivv[b], stk);
     if (threadIdx.x == 0) infov[b] = info;
 }
 
