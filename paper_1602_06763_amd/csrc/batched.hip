@@ -44,11 +44,13 @@ struct TrsmLds {
 
 template <typename T>
 struct PanelLdsB {
-    T P[kBatchMaxGe][kLuLeaf + 1];
+    T F[kBatchMaxGe][kLuLeaf + 1];   // finished entries: multipliers below, U rows on and above the diagonal
+    T slotP[kLuLeaf], slotJ[kLuLeaf];   // the pivot row's window; row j's window when the two trade places
     unsigned long long rk[4];
     unsigned rp[4];
-    int piv[kLuLeaf];   // panel row interchanged with row j at step j (j itself when none)
-    int zfirst;         // first exactly zero pivot, global 1-based column; 0 = none
+    int piv[kLuLeaf];        // panel row interchanged with row j at step j (j itself when none)
+    int pos[kBatchMaxGe];    // after the panel: the panel row whose content sits at each position
+    int zfirst;              // first exactly zero pivot, global 1-based column; 0 = none
 };
 
 template <typename T>
@@ -254,29 +256,36 @@ __device__ __forceinline__ int potrf_b(int n, T *A, long long si, long long sj, 
 }
 
 // LU panel of the columns c0..c0+w-1 (w <= 32) over the rows c0..n-1 of the
-// n×n matrix A (leading dimension lda), one row per thread, in LDS. Per
-// column j: the pivot among rows >= j, its row interchanged with row j when
-// its value is nonzero, the column below divided by the pivot (left as it is
-// for an exactly zero pivot), and the rank-1 update of the panel's remaining
-// columns. ipiv gets the pivot rows (global, 1-based); afterwards the panel's
-// interchanges are applied to every other column of the matrix. Returns the
-// first exactly zero pivot column (global, 1-based) or 0.
+// n×n matrix A (leading dimension lda). Thread t owns the row at panel
+// position t and keeps its not yet factored columns in registers as a sliding
+// window (x[q] is column j+q at step j). Per column j: the pivot among rows
+// >= j (largest magnitude, lowest position on ties, a NaN never wins); when
+// its value is nonzero the pivot row and row j trade places (their windows
+// through LDS, their finished multipliers in LDS); the column below is divided
+// by the pivot (left as it is for an exactly zero pivot) and the rank-1 update
+// is applied to the windows. ipiv gets the pivot rows (global, 1-based). The
+// finished panel is written once at the end, and the panel's interchanges are
+// then applied to every other column of the matrix as one gather of the
+// touched rows (at most 2w per column). Returns the first exactly zero pivot
+// column (global, 1-based) or 0.
 template <typename T>
 __device__ __forceinline__ int wg_getf2(int n, T *A, long long lda, int c0, int w, int *ipiv) {
+    constexpr int W = kLuLeaf;
     PanelLdsB<T> &P = blds<T>().pl;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int mp = n - c0;   // panel rows, <= kBatchMaxGe
-    for (int q = 0; q < w; ++q)
-        if (tid < mp) P.P[tid][q] = A[(c0 + tid) + (long long)(c0 + q) * lda];
+    T x[W];
+    {
+        const int r = min(tid, mp - 1);
+#pragma unroll
+        for (int q = 0; q < W; ++q) x[q] = A[(c0 + r) + (long long)(c0 + min(q, w - 1)) * lda];
+    }
     if (tid == 0) P.zfirst = 0;
-    __syncthreads();
     for (int j = 0; j < w; ++j) {
-        const int i = tid;
-        const T xij = P.P[min(i, mp - 1)][j];
-        const unsigned long long key = cand_key(fabs((double)xij), i >= j && i < mp);
+        const unsigned long long key = cand_key(fabs((double)x[0]), tid >= j && tid < mp);
         unsigned long long wk;
         unsigned wp;
-        wave_winner(key, (unsigned)i, wk, wp);
+        wave_winner(key, (unsigned)tid, wk, wp);
         if (lane == 0) {
             P.rk[wave] = wk;
             P.rp[wave] = wp;
@@ -297,33 +306,73 @@ __device__ __forceinline__ int wg_getf2(int n, T *A, long long lda, int c0, int 
             ipiv[c0 + j] = c0 + p + 1;
             if (!nz && P.zfirst == 0) P.zfirst = c0 + j + 1;
         }
-        if (moved && tid < w) {
-            const T t1 = P.P[j][tid];
-            P.P[j][tid] = P.P[p][tid];
-            P.P[p][tid] = t1;
+        // the pivot row's window to slotP; row j's to slotJ when they trade places;
+        // the finished multipliers of the two rows trade places as well
+        if (tid == (moved ? p : j)) {
+#pragma unroll
+            for (int q = 0; q < W; ++q) P.slotP[q] = x[q];
+        }
+        if (moved && tid == j) {
+#pragma unroll
+            for (int q = 0; q < W; ++q) P.slotJ[q] = x[q];
+        }
+        if (moved && tid < j) {
+            const T t1 = P.F[j][tid];
+            P.F[j][tid] = P.F[p][tid];
+            P.F[p][tid] = t1;
         }
         __syncthreads();
-        if (i > j && i < mp) {
-            const T piv = P.P[j][j];
-            const T x = P.P[i][j];
-            const T l = nz ? x / piv : x;
-            P.P[i][j] = l;
-            for (int q = j + 1; q < w; ++q) P.P[i][q] -= l * P.P[j][q];
+        if (moved && tid == p) {
+#pragma unroll
+            for (int q = 0; q < W; ++q) x[q] = P.slotJ[q];
         }
-        __syncthreads();
+        // row j of U, and the multipliers and rank-1 update below it
+        if (tid < w - j) P.F[j][j + tid] = P.slotP[tid];
+        const T piv = P.slotP[0];
+        const T l = nz ? x[0] / piv : x[0];
+        const bool below = tid > j && tid < mp;
+        if (below) P.F[tid][j] = l;
+        const T lk = below ? l : T(0);
+#pragma unroll
+        for (int q = 0; q < W - 1; ++q) x[q] = x[q + 1] - lk * P.slotP[q + 1];
     }
-    for (int q = 0; q < w; ++q)
-        if (tid < mp) A[(c0 + tid) + (long long)(c0 + q) * lda] = P.P[tid][q];
-    for (int col = tid; col < n; col += 256) {
-        if (col >= c0 && col < c0 + w) continue;
-        T *cp = A + (long long)col * lda + c0;
+    __syncthreads();
+    if (tid < mp) {
+        for (int q = 0; q < w; ++q) A[(c0 + tid) + (long long)(c0 + q) * lda] = P.F[tid][q];
+        P.pos[tid] = tid;
+    }
+    __syncthreads();
+    if (tid == 0) {
         for (int j = 0; j < w; ++j) {
             const int p = P.piv[j];
             if (p != j) {
-                const T t1 = cp[j];
-                cp[j] = cp[p];
-                cp[p] = t1;
+                const int t1 = P.pos[j];
+                P.pos[j] = P.pos[p];
+                P.pos[p] = t1;
             }
+        }
+    }
+    __syncthreads();
+    // every other column: position e of the touched set takes the content of row pos[e]
+    {
+        const int e = tid & 63, cg = tid >> 6;
+        const int te = e < w ? e : (e < 2 * w ? P.piv[e - w] : 0);
+        const int se = P.pos[te];
+        const bool act = e < 2 * w && se != te;
+        for (int col0 = 0; col0 < n; col0 += 32) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int col = min(col0 + cg + 4 * u, n - 1);
+                v[u] = A[(c0 + se) + (long long)col * lda];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int col = col0 + cg + 4 * u;
+                if (act && col < n && (col < c0 || col >= c0 + w)) A[(c0 + te) + (long long)col * lda] = v[u];
+            }
+            __syncthreads();
         }
     }
     const int zf = P.zfirst;
