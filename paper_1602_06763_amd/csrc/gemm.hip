@@ -62,6 +62,10 @@ struct GemmArgs {
     long long ldc;
     int tiles_m, tiles_n, ntiles;
     const int *abort;  // non-null: skip all work when *abort != 0
+    // Triangular tail: when tail_T > 0 the launch covers, with tiles of half
+    // the edge, the parent tiles tail_first.. of the band enumeration of a
+    // tail_T-tile triangle (four quarters per parent, consecutive).
+    int tail_T, tail_first;
 };
 
 // Map the hardware workgroup id to a logical tile id, giving each of the 8 XCDs
@@ -124,7 +128,15 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
         tn = r / gm;
     } else {
         int t, u;
-        tri_band_tile(tile, g.tiles_m, t, u);
+        if (g.tail_T > 0) {
+            const int q = tile & 3;
+            tri_band_tile(g.tail_first + (tile >> 2), g.tail_T, t, u);
+            t = 2 * t + (q >> 1);
+            u = 2 * u + (q & 1);
+            if (u > t) return;   // the quarter above the diagonal of a diagonal parent
+        } else {
+            tri_band_tile(tile, g.tiles_m, t, u);
+        }
         if (TRI == 1) { tm = t; tn = u; }   // lower: tm >= tn
         else { tm = u; tn = t; }            // upper: tm <= tn
     }
@@ -262,22 +274,45 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
 }
 
 template <typename TL, typename TA, typename TB, typename TC, bool TRA, bool TRB, int TRI, int BM>
-static void launch_k1(Ctx &c, const GemmArgs<TA, TB, TC> &args0) {
+static void launch_k1(Ctx &c, const GemmArgs<TA, TB, TC> &args0, int ntiles = -1) {
     GemmArgs<TA, TB, TC> a = args0;
     a.tiles_m = (int)((a.m + BM - 1) / BM);
     a.tiles_n = (int)((a.n + BM - 1) / BM);
-    a.ntiles = TRI ? a.tiles_m * (a.tiles_m + 1) / 2 : a.tiles_m * a.tiles_n;
+    a.ntiles = ntiles >= 0 ? ntiles : (TRI ? a.tiles_m * (a.tiles_m + 1) / 2 : a.tiles_m * a.tiles_n);
     if (a.ntiles <= 0) return;
     const int grid = (a.ntiles + 7) / 8 * 8;
     rl_launch(c, gemm_k1<TL, TA, TB, TC, TRA, TRB, TRI, BM, BM>, dim3(grid), dim3(256), 0, a);
     RL_CHECK(hipGetLastError());
 }
 
+// Tiles of the last, partly filled round of a triangular launch on 128-tiles
+// (two workgroups per CU), when that round is at most half full: they are run
+// afterwards as 64-tiles, four per parent tile, so the round's work is spread
+// over more CUs instead of leaving most of them idle. 0 = no split.
+static int tri_tail_tiles(const Ctx &c, long long m) {
+    const long long T = (m + 127) / 128, tiles = T * (T + 1) / 2, slots = 2LL * c.num_cu;
+    const long long r = tiles % slots;
+    return (tiles > slots && r > 0 && 2 * r <= slots) ? (int)r : 0;
+}
+
 template <typename TL, typename TA, typename TB, typename TC, bool TRA, bool TRB, int TRI>
 static void dispatch_tile(Ctx &c, const GemmArgs<TA, TB, TC> &a) {
     const long long big = ((a.m + 127) / 128) * ((a.n + 127) / 128) / (TRI ? 2 : 1);
-    if (big >= 2LL * c.num_cu) launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 128>(c, a);
-    else launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 64>(c, a);
+    if (big >= 2LL * c.num_cu) {
+        const int r = TRI ? tri_tail_tiles(c, a.m) : 0;
+        if (r > 0) {
+            const int T = (int)((a.m + 127) / 128), tiles = T * (T + 1) / 2;
+            launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 128>(c, a, tiles - r);
+            GemmArgs<TA, TB, TC> t = a;
+            t.tail_T = T;
+            t.tail_first = tiles - r;
+            launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 64>(c, t, 4 * r);
+        } else {
+            launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 128>(c, a);
+        }
+    } else {
+        launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 64>(c, a);
+    }
 }
 
 template <typename TL, typename TA, typename TB, typename TC>
@@ -516,13 +551,17 @@ void gemm(Ctx &c, Mfma mode, char ta, char tb, char tri, long long m, long long 
     const bool big = ((m + 127) / 128) * ((n + 127) / 128) / (tri ? 2 : 1) >= 2LL * c.num_cu;
     const int kind = mode == Mfma::F64 ? (tri ? PK_SYRK : (big ? PK_GEMM_BIG : PK_GEMM))
                                        : (tri ? PK_SYRK_LP : PK_GEMM_LP);
-    trace_kernel_begin(c);
+    // a triangular update with a split-off tail is two launches: timed as a region
+    const bool two = tri && big && (mode == Mfma::F64 || mode == Mfma::F32) && tri_tail_tiles(c, m) > 0;
+    if (two) trace_begin(c, kind);
+    else trace_kernel_begin(c);
     if (mode == Mfma::F64) dispatch<double>(c, ta, tb, tri, a);
     else if (mode == Mfma::F32) dispatch<float>(c, ta, tb, tri, a);
     else dispatch_half(c, mode, ta, tb, tri, a);
     const double bytes = (double)sizeof(TA) * m * k + (double)sizeof(TB) * k * n +
                          2.0 * sizeof(TC) * m * n / (tri ? 2.0 : 1.0);
-    trace_kernel_end(c, kind, flops, bytes);
+    if (two) trace_end(c, kind, flops, bytes);
+    else trace_kernel_end(c, kind, flops, bytes);
 }
 
 template void gemm<double, double, double>(Ctx &, Mfma, char, char, char, long long, long long,
