@@ -23,7 +23,8 @@ n = 8192 (``--inv-n``); ``variants`` times dpotrf with uplo = 'U' and the
 single-precision spotrf / sgetrf at the benchmark size (``--no-variants``
 skips them); ``batched`` times one call of each batched routine over 20000
 matrices of uneven sizes (``--batch-count``; SPD n in [8, 512], general n in
-[8, 256]) in FP64 and FP32.
+[8, 256]) in FP64 and FP32; ``--mixed-sweep`` adds the mixed solves over
+kappa in {1e2, 1e6, 1e10} x nrhs in {1, 16, 64} x {fp32, fp16, bf16}.
 
 Prints ONE JSON line. ``--gpus N`` with N > 1 exits: the library runs on one GPU.
 ``--copy-calib MB`` only runs a plain device copy of that size 20 times (the
@@ -66,6 +67,8 @@ def parse():
     p.add_argument("--target-n", type=int, default=32768,
                    help="also time one dpotrf + dgetrf at this size (0: skip)")
     p.add_argument("--no-variants", action="store_true", help="skip the uplo = 'U' and FP32 timings")
+    p.add_argument("--mixed-sweep", action="store_true",
+                   help="also time the mixed solves over kappa x nrhs x precision (about a minute)")
     p.add_argument("--batch-count", type=int, default=20000,
                    help="matrices per batched routine (SPD n in [8, 512], general n in [8, 256]); 0 skips")
     p.add_argument("--inv-n", type=int, default=8192,
@@ -373,6 +376,72 @@ def batched(count: int, stream, reps: int = 3, seed: int = 4):
     return out
 
 
+def mixed_sweep(n: int, stream, reps: int = 2):
+    """The mixed-precision solves over the grid of condition numbers (1e2, 1e6,
+    1e10), right-hand-side counts (1, 16, 64) and factorization precisions
+    (fp32, fp16, bf16), SPD and general, against the FP64 solve of the same
+    system (potrf + potrs, getrf + getrs); each time the median of ``reps``
+    calls after an untimed one. One conditioned matrix per kind and condition
+    number; smaller right-hand-side counts take the leading columns of b."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1602_06763_amd as rl
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(call):
+        ts, r = [], None
+        for i in range(reps + 1):
+            torch.cuda.synchronize()
+            e0, e1 = ev(), ev()
+            e0.record(stream)
+            r = call()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if i:
+                ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts)), r
+
+    rows = []
+    for kind in ("spd", "general"):
+        fp64 = {}
+        for kappa in (1e2, 1e6, 1e10):
+            M, b, _ = gen.conditioned_torch(n, kappa, kind, nrhs=64, seed=5, device="cuda")
+            for nrhs in (1, 16, 64):
+                bb = b[:, :nrhs]
+                if nrhs not in fp64:
+                    W = torch.empty_like(M.T).T
+                    Bw = torch.empty_like(bb.T).T
+                    piv = torch.zeros(n, dtype=torch.int32, device="cuda")
+
+                    def solve64():
+                        W.copy_(M)
+                        Bw.copy_(bb)
+                        if kind == "spd":
+                            return rl.potrf(W, "L") or rl.potrs(W, Bw, "L")
+                        return rl.getrf(W, piv) or rl.getrs(W, piv, Bw, "N")
+
+                    fp64[nrhs], info = timed(solve64)
+                    assert info == 0
+                    del W, Bw
+                X = torch.zeros_like(bb.T).T
+                pv = torch.zeros(n, dtype=torch.int32, device="cuda")
+                for prec in ("fp32", "fp16", "bf16"):
+                    if kind == "spd":
+                        ms, r = timed(lambda: rl.posv_mixed(M, bb, X, "L", prec))
+                    else:
+                        ms, r = timed(lambda: rl.gesv_mixed(M, pv, bb, X, prec))
+                    rows.append({"kind": kind, "kappa": kappa, "nrhs": nrhs, "prec": prec, "ms": round(ms, 3),
+                                 "fp64_solve_ms": round(fp64[nrhs], 3), "speedup": round(fp64[nrhs] / ms, 3),
+                                 "info": r[0], "iter": r[1], "berr": r[2]})
+                del X
+            del M, b
+            torch.cuda.empty_cache()
+    return {"n": n, "cases": rows}
+
+
 def copy_calibration(mb: float):
     import torch
 
@@ -565,6 +634,8 @@ def main():
         out["variants"] = variants(n, stream)
     if args.batch_count > 0:
         out["batched"] = batched(args.batch_count, stream)
+    if args.mixed_sweep:
+        out["mixed_sweep"] = mixed_sweep(n, stream)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_n1)
     print(json.dumps(out))

@@ -33,7 +33,7 @@ constexpr int kBatchMaxGe = 256;    // batched LU: largest matrix
 constexpr int kPanelRows = 512;     // panel rows per workgroup (two per thread)
 constexpr int kRecWords = 72;       // 64-bit words per panel exchange record
 constexpr int kRecSlots = kPanelMaxWG + 1;   // per step: one per workgroup, one for row d
-constexpr int kTrsvMaxRhs = 32;     // left-side solves with at most this many right-hand sides
+constexpr int kTrsvMaxRhs = 8;     // left-side solves with at most this many right-hand sides use TRSV
                                     // take the single-launch blocked solve
 constexpr int kLaswpBlock = 512;    // LU nodes wider than this apply interchanges in batches
 constexpr long long kLaswpBatchRows = 32768;   // batches need m <= this (a column's rows in registers)

@@ -351,22 +351,28 @@ __global__ __launch_bounds__(256) void trsv_k(const TT *__restrict__ T, TB *__re
                 for (int q = 0; q < NR; ++q) xs[w][lane][q] = 0.0;   // so the product needs no bounds
             } else {
                 unsigned long long *src = a.xw + (size_t)(c0 + lane) * 16;
+                // every word of the row's solutions in one round trip, polled
+                // together until all carry this solve's epoch
+                unsigned long long lo[NR], hi[NR];
+                unsigned spins = 0;
+                while (true) {
 #pragma unroll
-                for (int q = 0; q < NR; ++q) {
-                    if (q < nq) {
-                        unsigned long long lo, hi;
-                        unsigned spins = 0;
-                        while (true) {
-                            lo = __hip_atomic_load(&src[2 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            hi = __hip_atomic_load(&src[2 * q + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            if ((lo >> 32) == a.epoch && (hi >> 32) == a.epoch) break;
-                            if (++spins > (1u << 22)) { atomicExch(&a.st->error, 2); break; }
+                    for (int q = 0; q < NR; ++q) {
+                        lo[q] = hi[q] = (unsigned long long)a.epoch << 32;
+                        if (q < nq) {
+                            lo[q] = __hip_atomic_load(&src[2 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            hi[q] = __hip_atomic_load(&src[2 * q + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         }
-                        xs[w][lane][q] = __hiloint2double((int)(unsigned)hi, (int)(unsigned)lo);
-                    } else {
-                        xs[w][lane][q] = 0.0;
                     }
+                    bool fresh = true;
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) fresh = fresh && (lo[q] >> 32) == a.epoch && (hi[q] >> 32) == a.epoch;
+                    if (fresh) break;
+                    if (++spins > (1u << 22)) { atomicExch(&a.st->error, 2); break; }
                 }
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    xs[w][lane][q] = q < nq ? __hiloint2double((int)(unsigned)hi[q], (int)(unsigned)lo[q]) : 0.0;
             }
             __builtin_amdgcn_wave_barrier();
             // the block's solution from LDS in one batch of reads, then the
