@@ -28,7 +28,7 @@ struct DevState {
     int num_cu = 256;
     // single-launch triangular solve
     unsigned long long *trsv_x = nullptr;   // epoch-tagged solution words
-    size_t trsv_x_rows = 0;
+    size_t trsv_x_words = 0;
     unsigned long long *trsv_ticket = nullptr;
     unsigned long long trsv_tickets = 0;
     unsigned int trsv_epoch = 0;
@@ -151,24 +151,23 @@ unsigned long long *panel_records(Ctx &c, unsigned int *epoch) {
     return d.panel_rec;
 }
 
-TrsvWork trsv_work(Ctx &c, long long m, int nb, int launches) {
+TrsvWork trsv_work(Ctx &c, long long m, int nb, int launches, long long row_words, int tickets_per_block) {
     TrsvWork w;
-    (void)nb;
     std::lock_guard<std::mutex> lk(g_mu);
     DevState &d = g_dev[c.device];
-    if (d.trsv_x_rows < (size_t)m) {
+    const long long words = m * row_words;
+    if (d.trsv_x_words < (size_t)words) {
         if (d.trsv_x) { RL_CHECK(hipStreamSynchronize(c.stream)); RL_CHECK(hipFree(d.trsv_x)); }
         d.trsv_x = nullptr;
-        const long long words = m * 16;
         if (hipMalloc(&d.trsv_x, (size_t)words * sizeof(unsigned long long)) != hipSuccess) {
-            d.trsv_x_rows = 0;
+            d.trsv_x_words = 0;
             launch_error(hipErrorOutOfMemory);
             return w;
         }
         // epochs start at 1, so zeroed words never match
         hipLaunchKernelGGL(fill_u64_k, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, c.stream, d.trsv_x,
                            words, 0ull);
-        d.trsv_x_rows = (size_t)m;
+        d.trsv_x_words = (size_t)words;
     }
     if (!d.trsv_ticket) {
         RL_CHECK(hipMalloc(&d.trsv_ticket, sizeof(unsigned long long)));
@@ -179,7 +178,7 @@ TrsvWork trsv_work(Ctx &c, long long m, int nb, int launches) {
     w.ticket = d.trsv_ticket;
     w.ticket_base = d.trsv_tickets;
     w.epoch = d.trsv_epoch + 1;
-    d.trsv_tickets += (unsigned long long)nb * (unsigned long long)launches;
+    d.trsv_tickets += (unsigned long long)nb * (unsigned long long)launches * (unsigned long long)tickets_per_block;
     d.trsv_epoch += (unsigned)launches;
     return w;
 }

@@ -33,7 +33,7 @@ constexpr int kBatchMaxGe = 256;    // batched LU: largest matrix
 constexpr int kPanelRows = 512;     // panel rows per workgroup (two per thread)
 constexpr int kRecWords = 72;       // 64-bit words per panel exchange record
 constexpr int kRecSlots = kPanelMaxWG + 1;   // per step: one per workgroup, one for row d
-constexpr int kTrsvMaxRhs = 8;     // left-side solves with at most this many right-hand sides use TRSV
+constexpr int kTrsvMaxRhs = 64;    // left-side solves with at most this many right-hand sides use TRSV
                                     // take the single-launch blocked solve
 constexpr int kLaswpBlock = 512;    // LU nodes wider than this apply interchanges in batches
 constexpr long long kLaswpBatchRows = 32768;   // batches need m <= this (a column's rows in registers)
@@ -230,7 +230,8 @@ struct TrsvWork {
     unsigned int epoch = 0;
 };
 // Reserves ticket and epoch ranges for ceil(nrhs/8) launches of nb blocks.
-TrsvWork trsv_work(Ctx &c, long long m, int nb, int launches = 4);  // records a HIP failure in the calling thread's state
+TrsvWork trsv_work(Ctx &c, long long m, int nb, int launches = 4, long long row_words = 16,
+                   int tickets_per_block = 1);  // records a HIP failure in the calling thread's state
 
 }  // namespace rl
 

@@ -254,6 +254,7 @@ struct TrsvArgs {
     unsigned long long *xw;   // [n][8][2] epoch-tagged halves of x
     DevStatus *st;
     const double *dinv;       // DINV: inverses of the diagonal blocks of op(T), 64×64 column-major each
+    int nch;                  // trsv16_k: chunks of 16 right-hand sides solved side by side
 };
 
 __device__ __forceinline__ double rl_readlane(double x, int l) {
@@ -454,6 +455,132 @@ __global__ __launch_bounds__(256) void trsv_k(const TT *__restrict__ T, TB *__re
 }
 
 // ---------------------------------------------------------------------------
+// The same blocked solve for 2..64 right-hand sides, 16 per chain, all chains
+// in one launch: ticket t takes block t / nch of chunk t % nch, so blocks of
+// every chunk are dispatched in order and a workgroup only waits for blocks
+// with smaller tickets. Waves 1-3 multiply the tiles of the earlier blocks
+// with those blocks' solutions on the matrix cores (64 rows × 16 right-hand
+// sides per tile, the solution words of a block polled in one round trip);
+// wave 0 takes the block's right-hand sides, subtracts the three partial sums
+// and solves with the diagonal block (staged in LDS by all waves) by
+// substitution (solve64). Solutions are published as epoch-tagged words, 32
+// per row and chunk.
+// ---------------------------------------------------------------------------
+template <typename TT, bool FWD>
+__global__ __launch_bounds__(256) void trsv16_k(const TT *__restrict__ T, double *__restrict__ B, TrsvArgs a) {
+    typedef LeafMfma<double> Op;
+    typedef typename Op::acc_t acc_t;
+    __shared__ double Nsh[64][65];
+    __shared__ double Xs[64][17];
+    __shared__ double red[3][64][17];
+    __shared__ int bsh;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) bsh = (int)(atomicAdd(a.ticket, 1ull) - a.ticket_base);
+    __syncthreads();
+    const int nch = a.nch, b = bsh / nch, ch = bsh % nch, nb = a.nb;
+    const long long n = a.n, ldt = a.ldt, ldb = a.ldb;
+    const int pb = FWD ? b : nb - 1 - b;
+    const long long r0 = (long long)pb * 64;
+    const int nrow = (int)min(64LL, n - r0);
+    const int nq = min(16, a.nrhs - 16 * ch);
+    double *Bc = B + (long long)(16 * ch) * ldb;
+    unsigned long long *xw = a.xw + (size_t)ch * (size_t)n * 32;
+    const unsigned long long ET = (unsigned long long)a.epoch << 32;
+    auto opT = [&](long long r, long long c) { return (double)(a.trans ? T[c + r * ldt] : T[r + c * ldt]); };
+
+    // the diagonal block, the identity beyond the triangle
+    for (int idx = tid; idx < 64 * 64; idx += 256) {
+        const int i = idx & 63, j = idx >> 6;
+        const bool in = i < nrow && j < nrow && (FWD ? j <= i : j >= i);
+        const double v = opT(r0 + min(i, nrow - 1), r0 + min(j, nrow - 1));
+        Nsh[i][j] = in ? v : (i == j ? 1.0 : 0.0);
+    }
+    if (wave == 0) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = (lane >> 4) + 4 * u, q = lane & 15;
+            const double v = Bc[r0 + min(e, nrow - 1) + (long long)min(q, nq - 1) * ldb];
+            Xs[e][q] = (e < nrow && q < nq) ? v : 0.0;
+        }
+    } else {
+        const int w = wave - 1, lr = lane & 15, lk = lane >> 4;
+        acc_t acc[4];
+#pragma unroll
+        for (int i4 = 0; i4 < 4; ++i4) acc[i4] = acc_t{0, 0, 0, 0};
+        for (int jj = w; jj < b; jj += 3) {
+            const int pj = FWD ? jj : nb - 1 - jj;
+            const long long c0 = (long long)pj * 64;
+            const int ncol = (int)min(64LL, n - c0);
+            // the tile first, its loads in flight while the solution is polled
+            double av[16][4];
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                const int k = 4 * kk + lk;
+#pragma unroll
+                for (int i4 = 0; i4 < 4; ++i4) {
+                    const int i = 16 * i4 + lr;
+                    const double v = opT(r0 + min(i, nrow - 1), c0 + min(k, ncol - 1));
+                    av[kk][i4] = (i < nrow && k < ncol) ? v : 0.0;
+                }
+            }
+            asm volatile("" ::: "memory");
+            unsigned long long lo[16], hi[16];
+            unsigned spins = 0;
+            while (true) {
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) {
+                    const int k = 4 * kk + lk;
+                    lo[kk] = hi[kk] = ET;
+                    if (k < ncol && lr < nq) {
+                        const unsigned long long *src = xw + (size_t)(c0 + k) * 32 + 2 * lr;
+                        lo[kk] = __hip_atomic_load(&src[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        hi[kk] = __hip_atomic_load(&src[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                bool fresh = true;
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk)
+                    fresh = fresh && (unsigned)(lo[kk] >> 32) == a.epoch && (unsigned)(hi[kk] >> 32) == a.epoch;
+                if (fresh) break;
+                if (++spins > (1u << 22)) { atomicExch(&a.st->error, 2); break; }
+            }
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                const int k = 4 * kk + lk;
+                const double bv = (k < ncol && lr < nq) ? __hiloint2double((int)(unsigned)hi[kk], (int)(unsigned)lo[kk])
+                                                        : 0.0;
+#pragma unroll
+                for (int i4 = 0; i4 < 4; ++i4) acc[i4] = Op::mma(av[kk][i4], bv, acc[i4]);
+            }
+        }
+#pragma unroll
+        for (int i4 = 0; i4 < 4; ++i4)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[w][16 * i4 + Op::row(lane, v)][lane & 15] = acc[i4][v];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = (lane >> 4) + 4 * u, q = lane & 15;
+            Xs[e][q] -= (red[0][e][q] + red[1][e][q]) + red[2][e][q];
+        }
+        solve64<double, FWD>(Nsh, Xs, nrow, a.unit, lane);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = (lane >> 4) + 4 * u, q = lane & 15;
+            if (e < nrow && q < nq) {
+                const double x = Xs[e][q];
+                Bc[r0 + e + (long long)q * ldb] = x;
+                unsigned long long *dst = xw + (size_t)(r0 + e) * 32 + 2 * q;
+                __hip_atomic_store(&dst[0], ET | (unsigned)__double2loint(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&dst[1], ET | (unsigned)__double2hiint(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Inverses of the 64×64 diagonal blocks of op(T) (rows/columns beyond m hold
 // the identity), one workgroup per block: the leaf substitution against the
 // identity, written out in full (zeros included), column-major per block.
@@ -519,6 +646,30 @@ template <typename TT, typename TB>
 void trsv(Ctx &c, bool lower_eff, bool trans, bool unit, long long m, long long nrhs, const TT *T,
           long long ldt, TB *B, long long ldb, const double *dinv) {
     const int nb = (int)((m + 63) / 64);
+    if (nrhs > 1) {
+        if constexpr (std::is_same<TB, double>::value) {
+            const int nch = (int)((nrhs + 15) / 16);
+            TrsvWork wk = trsv_work(c, m, nb, 1, 32LL * nch, nch);
+            if (!wk.xw) return;
+            trace_begin(c, PK_TRSM_LEAF);
+            TrsvArgs a{};
+            a.n = m; a.nrhs = (int)nrhs; a.nb = nb; a.nch = nch;
+            a.ldt = ldt; a.ldb = ldb;
+            a.trans = trans; a.lower_eff = lower_eff; a.unit = unit;
+            a.epoch = wk.epoch;
+            a.ticket = wk.ticket;
+            a.ticket_base = wk.ticket_base;
+            a.xw = wk.xw;
+            a.st = c.dstat;
+            if (lower_eff)
+                hipLaunchKernelGGL((trsv16_k<TT, true>), dim3(nb * nch), dim3(256), 0, c.stream, T, B, a);
+            else
+                hipLaunchKernelGGL((trsv16_k<TT, false>), dim3(nb * nch), dim3(256), 0, c.stream, T, B, a);
+            RL_CHECK(hipGetLastError());
+            trace_end(c, PK_TRSM_LEAF, (double)m * m * nrhs, (double)sizeof(TT) * m * m / 2.0 + 16.0 * m * nrhs);
+            return;
+        }
+    }
     TrsvWork wk = trsv_work(c, m, nb, (int)((nrhs + 7) / 8));
     if (!wk.xw) return;
     trace_begin(c, PK_TRSM_LEAF);

@@ -72,7 +72,7 @@ def test_trsm(side, uplo, trans, diag):
 @pytest.mark.parametrize("uplo", ["L", "U"])
 @pytest.mark.parametrize("trans", ["N", "T"])
 @pytest.mark.parametrize("diag", ["N", "U"])
-@pytest.mark.parametrize("m,nrhs", [(1000, 1), (333, 3), (64, 8), (65, 9), (700, 20), (129, 33)])
+@pytest.mark.parametrize("m,nrhs", [(1000, 1), (333, 3), (64, 8), (65, 9), (700, 20), (129, 33), (515, 47), (1000, 64)])
 def test_trsm_few_rhs(uplo, trans, diag, m, nrhs):
     """Left-side solves with few right-hand sides (the single-launch blocked solve)."""
     tri = np.tril(gen.general_uniform(m, m, seed=16)) if uplo == "L" else np.triu(gen.general_uniform(m, m, seed=16))
