@@ -10,12 +10,13 @@
 // or 256 rows (LU) stays in the L2 cache while its workgroup works on it; the
 // workgroup-level operations are:
 //   - potf2 leaf: the unblocked Cholesky of a <= 64 block in LDS (potf2_block);
-//   - LU leaf: a <= 32-column panel of all rows below the diagonal in LDS, one
-//     row per thread, partial pivoting with the pivot rule of the single-matrix
-//     panel (largest magnitude, lowest position on ties, a NaN never wins), the
-//     rows interchanged in place, and the panel's interchanges applied to every
-//     other column of the matrix before the recursion goes on (each interchange
-//     reaches every column once, in order, as in LAPACK's dgetrf);
+//   - LU leaf: a <= 32-column panel of all rows below the diagonal, one row
+//     per thread in registers, partial pivoting with the pivot rule of the
+//     single-matrix panel (largest magnitude, lowest position on ties, a NaN
+//     never wins), the pivot row and row j trading places through LDS, and the
+//     panel's interchanges applied to every other column of the matrix before
+//     the recursion goes on (each interchange reaches every column once, in
+//     order, as in LAPACK's dgetrf);
 //   - triangular solves by 64-row blocks of the triangle (solve64 on 16 vectors
 //     per wave) with the remaining rows updated on the matrix cores;
 //   - products C -= A·B by 64×64 tiles per workgroup on the matrix cores, K
