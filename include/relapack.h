@@ -22,7 +22,9 @@
  *     the call a no-op.
  *   - Every call is stream-ordered on the calling thread's library stream
  *     (relapack_set_stream) and returns after the work has completed, so info
- *     is valid on return.
+ *     is valid on return. Calls from several threads on one device run one
+ *     at a time (the per-device workspace is shared); each holds the device
+ *     until its work has completed.
  *   - info = 0: success. info = -k: argument k (counted in the C signature
  *     order below) is illegal; nothing was launched. info in (-2000, -1000]:
  *     a HIP runtime error e was reported (info = -1000 - e). info <= -2000:

@@ -36,6 +36,9 @@ struct DevState {
 
 DevState g_dev[kMaxDev];
 std::mutex g_mu;
+// One library call at a time per device: the status block, the panel's
+// exchange records, the solve's tickets and the workspace are per device.
+std::recursive_mutex g_call_mu[kMaxDev];
 
 struct TraceRec {
     int kind;
@@ -45,6 +48,7 @@ struct TraceRec {
 
 thread_local Ctx t_ctx;
 thread_local int t_err = 0;
+thread_local int t_locked = -1;   // device whose call lock this thread holds
 thread_local std::vector<TraceRec> t_trace;
 thread_local std::vector<hipEvent_t> t_evpool;
 thread_local size_t t_evused = 0;
@@ -233,6 +237,10 @@ static bool call_begin(Ctx &c, bool abort_on_info) {
     t_err = 0;
     ensure_device(c);
     if (t_err) return false;
+    if (t_locked < 0) {
+        g_call_mu[c.device].lock();
+        t_locked = c.device;
+    }
     c.abort_on_info = abort_on_info;
     c.level = 0;
     hipLaunchKernelGGL(reset_status_k, dim3(1), dim3(64), 0, c.stream, c.dstat);
@@ -244,10 +252,15 @@ static int call_end(Ctx &c) {
     if (!t_err) {
         RL_CHECK(hipMemcpyAsync(c.hstat, c.dstat, sizeof(DevStatus), hipMemcpyDeviceToHost, c.stream));
         RL_CHECK(hipStreamSynchronize(c.stream));
+    } else if (t_locked >= 0) {
+        (void)hipStreamSynchronize(c.stream);   // nothing of this call may still run once the lock is released
     }
-    if (t_err) return -1000 - t_err;
-    if (c.hstat->error) return -2000 - c.hstat->error;
-    return c.hstat->info;
+    const int r = t_err ? -1000 - t_err : (c.hstat->error ? -2000 - c.hstat->error : c.hstat->info);
+    if (t_locked >= 0) {
+        g_call_mu[t_locked].unlock();
+        t_locked = -1;
+    }
+    return r;
 }
 
 static inline bool is(char a, char b) { return a == b || a == (char)(b + ('a' - 'A')); }
@@ -297,8 +310,10 @@ int relapack_set_stream(void *stream) {
 void *relapack_get_stream(void) { return (void *)ctx().stream; }
 
 void relapack_finalize(void) {
-    std::lock_guard<std::mutex> lk(g_mu);
     for (int i = 0; i < kMaxDev; ++i) {
+        // the same lock order as a call: the device's call lock, then the state lock
+        std::lock_guard<std::recursive_mutex> call_lk(g_call_mu[i]);
+        std::lock_guard<std::mutex> lk(g_mu);
         DevState &d = g_dev[i];
         if (!d.init) continue;
         int cur = 0;
