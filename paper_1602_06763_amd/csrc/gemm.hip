@@ -103,10 +103,14 @@ __device__ __forceinline__ void tri_band_tile(int tile, int T, int &t, int &u) {
 }
 
 template <typename TL, typename TA, typename TB, typename TC, bool TRA, bool TRB, int TRI, int BM,
-          int BN>
+          int BN, bool VEC>
 __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
     constexpr int BK = 16;
-    constexpr int PAD = 1;
+    // VEC: each thread moves pairs of elements that are adjacent in memory
+    // (one 2-wide load per pair on full tiles; the host selects this only when
+    // both operands' base and leading dimension keep every pair aligned); the
+    // even pad keeps the pairs aligned in LDS as well.
+    constexpr int PAD = VEC ? 2 : 1;
     constexpr int MI = BM / 32, NI = BN / 32;
     constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
     typedef MfmaK1<TL> Op;
@@ -156,20 +160,45 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
     TA ra[EA];
     TB rb[EB];
 
-    // element coordinates of this thread's share of a K tile
+    // element coordinates of this thread's share of a K tile; with VEC,
+    // elements 2p and 2p+1 are neighbours along the operand's contiguous index
     auto a_coord = [&](int i, int &r, int &kk) {
-        if (!TRA) { r = tid % BM; kk = tid / BM + i * (256 / BM); }
-        else { kk = tid % BK; r = tid / BK + i * (256 / BK); }
+        if (VEC) {
+            const int p = i >> 1, h = i & 1;
+            if (!TRA) { r = 2 * (tid % (BM / 2)) + h; kk = tid / (BM / 2) + p * (512 / BM); }
+            else { kk = 2 * (tid % (BK / 2)) + h; r = tid / (BK / 2) + p * (512 / BK); }
+        } else {
+            if (!TRA) { r = tid % BM; kk = tid / BM + i * (256 / BM); }
+            else { kk = tid % BK; r = tid / BK + i * (256 / BK); }
+        }
     };
     auto b_coord = [&](int i, int &c, int &kk) {
-        if (TRB) { c = tid % BN; kk = tid / BN + i * (256 / BN); }
-        else { kk = tid % BK; c = tid / BK + i * (256 / BK); }
+        if (VEC) {
+            const int p = i >> 1, h = i & 1;
+            if (TRB) { c = 2 * (tid % (BN / 2)) + h; kk = tid / (BN / 2) + p * (512 / BN); }
+            else { kk = 2 * (tid % (BK / 2)) + h; c = tid / (BK / 2) + p * (512 / BK); }
+        } else {
+            if (TRB) { c = tid % BN; kk = tid / BN + i * (256 / BN); }
+            else { kk = tid % BK; c = tid / BK + i * (256 / BK); }
+        }
     };
+    typedef TA TA2 __attribute__((ext_vector_type(2)));
+    typedef TB TB2 __attribute__((ext_vector_type(2)));
 
     auto load_tiles = [&](long long k0) {
         const bool afull = (m0 + BM <= M) && (k0 + BK <= K);
         const bool bfull = (n0 + BN <= N) && (k0 + BK <= K);
-        if (afull) {
+        if (afull && VEC) {
+#pragma unroll
+            for (int i = 0; i < EA; i += 2) {
+                int r, kk;
+                a_coord(i, r, kk);
+                const long long gr = m0 + r, gk = k0 + kk;
+                const TA2 v = *(const TA2 *)(A + (TRA ? gk + gr * g.lda : gr + gk * g.lda));
+                ra[i] = v.x;
+                ra[i + 1] = v.y;
+            }
+        } else if (afull) {
 #pragma unroll
             for (int i = 0; i < EA; ++i) {
                 int r, kk;
@@ -188,7 +217,17 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
                 ra[i] = (gr < M && gk < K) ? A[TRA ? gk + gr * g.lda : gr + gk * g.lda] : TA(0);
             }
         }
-        if (bfull) {
+        if (bfull && VEC) {
+#pragma unroll
+            for (int i = 0; i < EB; i += 2) {
+                int c, kk;
+                b_coord(i, c, kk);
+                const long long gc = n0 + c, gk = k0 + kk;
+                const TB2 v = *(const TB2 *)(B + (TRB ? gc + gk * g.ldb : gk + gc * g.ldb));
+                rb[i] = v.x;
+                rb[i + 1] = v.y;
+            }
+        } else if (bfull) {
 #pragma unroll
             for (int i = 0; i < EB; ++i) {
                 int c, kk;
@@ -233,9 +272,16 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
         store_tiles(0);
         __syncthreads();
     }
+    // VEC (the 128-tile path): the next K tile goes to LDS right after the
+    // first quarter of the products (the other buffer was last read before the
+    // previous barrier), and the waves raise their issue priority while they
+    // feed the matrix cores; measured 2-7 % over storing after the last quarter
+    // at normal priority.
+    constexpr int STORE_AFTER = VEC ? 0 : BK / 4 - 1;
     for (long long kt = 0; kt < KT; ++kt) {
         const int buf = (int)(kt & 1);
         if (kt + 1 < KT) load_tiles((kt + 1) * BK);
+        if (VEC) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
@@ -248,8 +294,9 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
             for (int i = 0; i < MI; ++i)
 #pragma unroll
                 for (int j = 0; j < NI; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
+            if (ks == STORE_AFTER && kt + 1 < KT) store_tiles(buf ^ 1);
         }
-        if (kt + 1 < KT) store_tiles(buf ^ 1);
+        if (VEC) __builtin_amdgcn_s_setprio(0);
         __syncthreads();
     }
 
@@ -273,7 +320,8 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
             }
 }
 
-template <typename TL, typename TA, typename TB, typename TC, bool TRA, bool TRB, int TRI, int BM>
+template <typename TL, typename TA, typename TB, typename TC, bool TRA, bool TRB, int TRI, int BM,
+          bool VEC = false>
 static void launch_k1(Ctx &c, const GemmArgs<TA, TB, TC> &args0, int ntiles = -1) {
     GemmArgs<TA, TB, TC> a = args0;
     a.tiles_m = (int)((a.m + BM - 1) / BM);
@@ -281,7 +329,7 @@ static void launch_k1(Ctx &c, const GemmArgs<TA, TB, TC> &args0, int ntiles = -1
     a.ntiles = ntiles >= 0 ? ntiles : (TRI ? a.tiles_m * (a.tiles_m + 1) / 2 : a.tiles_m * a.tiles_n);
     if (a.ntiles <= 0) return;
     const int grid = (a.ntiles + 7) / 8 * 8;
-    rl_launch(c, gemm_k1<TL, TA, TB, TC, TRA, TRB, TRI, BM, BM>, dim3(grid), dim3(256), 0, a);
+    rl_launch(c, gemm_k1<TL, TA, TB, TC, TRA, TRB, TRI, BM, BM, VEC>, dim3(grid), dim3(256), 0, a);
     RL_CHECK(hipGetLastError());
 }
 
@@ -295,20 +343,28 @@ static int tri_tail_tiles(const Ctx &c, long long m) {
     return (tiles > slots && r > 0 && 2 * r <= slots) ? (int)r : 0;
 }
 
+// Pairs of adjacent elements of an operand can be read as one 2-wide load
+// when its base and every column start are aligned to the pair size.
+template <typename T>
+static bool pairs_aligned(const T *p, long long ld) {
+    return ((uintptr_t)p % (2 * sizeof(T))) == 0 && ld % 2 == 0;
+}
+
 template <typename TL, typename TA, typename TB, typename TC, bool TRA, bool TRB, int TRI>
 static void dispatch_tile(Ctx &c, const GemmArgs<TA, TB, TC> &a) {
     const long long big = ((a.m + 127) / 128) * ((a.n + 127) / 128) / (TRI ? 2 : 1);
     if (big >= 2LL * c.num_cu) {
         const int r = TRI ? tri_tail_tiles(c, a.m) : 0;
+        const int T = (int)((a.m + 127) / 128), tiles = T * (T + 1) / 2;
+        if (pairs_aligned(a.A, a.lda) && pairs_aligned(a.B, a.ldb))
+            launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 128, true>(c, a, r > 0 ? tiles - r : -1);
+        else
+            launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 128, false>(c, a, r > 0 ? tiles - r : -1);
         if (r > 0) {
-            const int T = (int)((a.m + 127) / 128), tiles = T * (T + 1) / 2;
-            launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 128>(c, a, tiles - r);
             GemmArgs<TA, TB, TC> t = a;
             t.tail_T = T;
             t.tail_first = tiles - r;
             launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 64>(c, t, 4 * r);
-        } else {
-            launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 128>(c, a);
         }
     } else if (TRI && ((a.m + 63) / 64) * ((a.m + 63) / 64 + 1) / 2 <= 4LL * c.num_cu) {
         // small triangular updates: 32-tiles give the chip four times the

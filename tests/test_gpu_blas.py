@@ -28,6 +28,59 @@ def test_gemm(ta, tb, m, n, k):
     assert np.abs(to_host(C) - ref).max() <= 4 * (k + 2) * U64 * max(1.0, np.abs(ref).max())
 
 
+def _dev_layout(a, layout):
+    """Device copy of a for the large-tile tests: 'pairs' gives an even leading
+    dimension and an aligned base (2-wide loads), 'odd_ld' an odd leading
+    dimension, 'odd_base' a base one element past an aligned address."""
+    rows = a.shape[0]
+    if layout == "pairs":
+        return to_dev(a, ld=rows + rows % 2), rows + rows % 2
+    if layout == "odd_ld":
+        return to_dev(a, ld=rows + 1 - rows % 2), rows + 1 - rows % 2
+    padded = np.vstack([np.zeros((1, a.shape[1])), a])
+    ld = rows + 2 - rows % 2
+    return to_dev(padded, ld=ld)[1:, :], ld
+
+
+@pytest.mark.parametrize("ta", ["N", "T"])
+@pytest.mark.parametrize("tb", ["N", "T"])
+@pytest.mark.parametrize("layout", ["pairs", "odd_ld", "odd_base"])
+def test_gemm_large_tiles(ta, tb, layout):
+    """Sizes that take the 128x128 tiles (at least two per CU), ragged in every
+    dimension, with operands whose adjacent elements pair up and with operands
+    that force element-wise loads."""
+    m, n, k = 2900, 2836, 37
+    a = gen.general_uniform(m if ta == "N" else k, k if ta == "N" else m, seed=11)
+    b = gen.general_uniform(k if tb == "N" else n, n if tb == "N" else k, seed=12)
+    c = gen.general_uniform(m, n, seed=13)
+    (A, lda), (B, ldb) = _dev_layout(a, layout), _dev_layout(b, layout)
+    C = to_dev(c, ld=m + 3)
+    assert rl.gemm(ta, tb, m, n, k, -1.0, A, lda, B, ldb, 0.5, C, m + 3) == 0
+    ref = 0.5 * c - (a if ta == "N" else a.T) @ (b if tb == "N" else b.T)
+    assert np.abs(to_host(C) - ref).max() <= 4 * (k + 2) * U64 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("uplo", ["L", "U"])
+@pytest.mark.parametrize("trans", ["N", "T"])
+@pytest.mark.parametrize("layout", ["pairs", "odd_ld"])
+def test_syrk_large_tiles(uplo, trans, layout):
+    """A triangular update on 128x128 tiles whose last, partly filled round runs
+    as 64x64 quarters (n = 4100: 561 tiles for 512 slots)."""
+    n, k = 4100, 20
+    a = gen.general_uniform(n if trans == "N" else k, k if trans == "N" else n, seed=14)
+    c = gen.general_uniform(n, n, seed=15)
+    A, lda = _dev_layout(a, layout)
+    C = to_dev(c)
+    assert rl.syrk(uplo, trans, n, k, -1.0, A, lda, 1.0, C, n) == 0
+    op = a if trans == "N" else a.T
+    ref = c - op @ op.T
+    got = to_host(C)
+    tri = np.tril_indices(n) if uplo == "L" else np.triu_indices(n)
+    other = np.triu_indices(n, 1) if uplo == "L" else np.tril_indices(n, -1)
+    assert np.abs(got[tri] - ref[tri]).max() <= 4 * (k + 2) * U64 * np.abs(ref).max()
+    assert np.array_equal(got[other], c[other])
+
+
 @pytest.mark.parametrize("uplo", ["L", "U"])
 @pytest.mark.parametrize("trans", ["N", "T"])
 def test_syrk_touches_one_triangle(uplo, trans):
