@@ -571,7 +571,7 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64, 4),
                 "traffic": round(traffic, 1) if traffic is not None else None,
-                "kernel": "gemm_k1<double,...,TRI=0,128,128> (FP64 GEMM, 128x128 tiles)",
+                "kernel": "gemm_k1<double,...,TRI=0,128,128,*> (FP64 GEMM, 128x128 tiles)",
                 "launches": d["launches"], "avg_launch_us": round(avg_s * 1e6, 3),
                 "flops_per_launch": round(d["flops"] / launches, 1),
                 "algorithmic_bytes_per_launch": round(d["bytes"] / launches, 1)}

@@ -275,8 +275,9 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
     // VEC (the 128-tile path): the next K tile goes to LDS right after the
     // first quarter of the products (the other buffer was last read before the
     // previous barrier), and the waves raise their issue priority while they
-    // feed the matrix cores; measured 2-7 % over storing after the last quarter
-    // at normal priority.
+    // feed the matrix cores. Measured at n = 4096 and 8192 against storing
+    // after the last quarter at normal priority with element-wise loads: from
+    // on par to 7 % faster, depending on the run.
     constexpr int STORE_AFTER = VEC ? 0 : BK / 4 - 1;
     for (long long kt = 0; kt < KT; ++kt) {
         const int buf = (int)(kt & 1);
