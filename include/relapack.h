@@ -30,8 +30,8 @@
  *     a HIP runtime error e was reported (info = -1000 - e). info <= -2000:
  *     an internal wait of the LU panel timed out (the result is unusable).
  *   - The library keeps a grow-only device workspace per device (status
- *     block, pivot bookkeeping, low-precision copies); relapack_finalize()
- *     releases it.
+ *     block, pivot bookkeeping, low-precision copies, the launch order of a
+ *     batch); relapack_finalize() releases it.
  *   - Integer arguments are 32-bit as in LAPACK; index arithmetic inside is
  *     64-bit.
  */
@@ -250,6 +250,9 @@ void relapack_sgetrf(int m, int n, float *A, int lda, int *ipiv, int *info);
  *   info[b] (device): 0, k > 0 (leading minor k not positive definite; that
  *   matrix's factorization stopped there), -2 (n[b] < 0 or n[b] > 512),
  *   -4 (lda[b] < max(1, n[b])).
+ *   Batches larger than the chip holds at once (two workgroups per CU) run
+ *   in order of size, largest first; the order (count ints) is computed on
+ *   the device into the library's workspace.
  * Returns 0, -1 (uplo), -2 (count < 0), -3 (a null array with count > 0),
  * or -1000 - hipError_t. Stream-ordered; returns after completion.
  */
@@ -264,7 +267,8 @@ int relapack_spotrf_batched(char uplo, int count, const int *n, float *const *A,
  *   to the caller's device array of n[b] ints (1-based pivot rows).
  *   info[b] (device): 0, k > 0 (U(k,k) exactly zero, the first such k; the
  *   factorization completes), -2 (n[b] < 0 or n[b] > 256), -4 (lda[b] <
- *   max(1, n[b])).
+ *   max(1, n[b])). Large batches run in order of size as in
+ *   relapack_dpotrf_batched.
  * Returns 0, -1 (count < 0), -2 (a null array with count > 0), or
  * -1000 - hipError_t. Stream-ordered; returns after completion.
  */

@@ -13,7 +13,8 @@ namespace rl {
 namespace {
 
 constexpr int kMaxDev = 16;
-constexpr int kScratchSlots = 10;   // 0-6 mixed solver, 7 LU row tracker, 8 correction-solve block inverses
+constexpr int kScratchSlots = 10;   // 0-6 mixed solver, 7 LU row tracker, 8 correction-solve block inverses,
+                                    // 9 launch order of a batch
 
 struct DevState {
     bool init = false;

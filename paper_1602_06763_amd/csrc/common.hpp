@@ -93,6 +93,7 @@ struct Ctx {
 Ctx &ctx();
 void ensure_device(Ctx &c);
 void *scratch(Ctx &c, int slot, size_t bytes);   // grow-only per-device workspace
+constexpr int kSlotBatchOrder = 9;                 // workspace slot: launch order of a batch
 // Exchange records of the cooperative LU panel ([kLuLeaf][kRecSlots][kRecWords]
 // words) and the first of kLuLeaf consecutive epochs reserved for one panel.
 unsigned long long *panel_records(Ctx &c, unsigned int *epoch);

@@ -224,3 +224,48 @@ def test_batched_many_uneven():
         res = np.linalg.norm(oracle.apply_ipiv(a, piv) - L @ U) / np.linalg.norm(a)
         assert res <= 10 * a.shape[0] * U64
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("routine", ["potrf", "getrf"])
+def test_batched_size_order_with_illegal_sizes(orc, routine):
+    """A batch larger than the chip holds at once (launched in order of size)
+    with illegal and empty matrices among the legal ones: every legal matrix
+    factored, every illegal one reported, in the caller's order."""
+    import torch
+
+    g = np.random.default_rng(9)
+    count = 700
+    ns = g.integers(1, 41, size=count)
+    mats = [gen.spd_bbt(int(n), seed=int(500 + i)) if routine == "potrf"
+            else gen.general_uniform(int(n), int(n), seed=int(500 + i)) for i, n in enumerate(ns)]
+    devs, ptrs, n, lda, info = _dev_batch(mats, [int(x) for x in ns])
+    too_big = 513 if routine == "potrf" else 257
+    bad_n = {3: too_big, 150: -1, 420: 0}
+    bad_ld = {77, 699}
+    for i, v in bad_n.items():
+        n[i] = v
+    for i in bad_ld:
+        lda[i] = int(ns[i]) - 1 if ns[i] > 1 else 0
+    if routine == "potrf":
+        assert rl.potrf_batched("L", count, n, ptrs, lda, info) == 0
+    else:
+        pivs = [torch.zeros(max(int(x), 1), dtype=torch.int32, device="cuda") for x in ns]
+        pptrs = torch.tensor([p.data_ptr() for p in pivs], dtype=torch.int64, device="cuda")
+        assert rl.getrf_batched(count, n, ptrs, lda, pptrs, info) == 0
+    got_info = info.cpu().numpy()
+    for i in range(count):
+        if i in bad_n:
+            assert got_info[i] == (0 if bad_n[i] == 0 else -2), i
+            continue
+        if i in bad_ld:
+            assert got_info[i] == -4, i
+            continue
+        assert got_info[i] == 0, i
+        f = to_host(devs[i])
+        if routine == "potrf":
+            ref, _ = orc.potrf(mats[i])
+            assert rel_fro(np.tril(f), np.tril(ref)) <= 1e-12, i
+        else:
+            ref, rpiv, _ = orc.getrf(mats[i])
+            assert np.array_equal(pivs[i].cpu().numpy()[: ns[i]], rpiv), i
+            assert rel_fro(f, ref) <= 1e-9, i
