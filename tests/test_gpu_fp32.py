@@ -84,3 +84,64 @@ def test_sgetrf_zero_pivot_completes():
     A = to_dev(_f32(a))
     piv = ipiv_dev(200)
     assert rl.sgetrf(A, piv) == 51
+
+
+def _dev_f32(a64, ld):
+    """FP64 CUDA matrix -> column-major FP32 CUDA view with leading dimension ld
+    (padding rows NaN)."""
+    import torch
+
+    m, n = a64.shape
+    buf = torch.full((n, ld), float("nan"), dtype=torch.float32, device="cuda")
+    buf[:, :m] = a64.T.float()
+    return buf.T[:m, :]
+
+
+@pytest.mark.parametrize("ld_extra", [0, 1])
+def test_spotrf_large_tiles(ld_extra):
+    """n = 8192: the top-level triangular update runs on 128x128 tiles, with
+    pairs of adjacent elements loaded together (even leading dimension) or one
+    by one (odd). Residual of the FP32 factor, computed in FP64 on the GPU."""
+    import torch
+
+    n = 8192
+    g = torch.Generator(device="cuda")
+    g.manual_seed(31)
+    B = torch.rand(n, n, dtype=torch.float64, device="cuda", generator=g) * 2 - 1
+    a = B @ B.T.contiguous() + n * torch.eye(n, dtype=torch.float64, device="cuda")
+    a = a.float().double()   # the matrix the FP32 routine sees
+    A = _dev_f32(a, n + ld_extra)
+    assert rl.spotrf(A, "L", n=n, lda=n + ld_extra) == 0
+    L = torch.tril(A.double().contiguous())
+    res = float(torch.linalg.norm(L @ L.T.contiguous() - a) / torch.linalg.norm(a))
+    assert res <= 10 * n * U32
+
+
+@pytest.mark.parametrize("ld_extra", [0, 1])
+def test_sgetrf_large_tiles(ld_extra):
+    """n = 8192: the top-level trailing update runs on 128x128 tiles, paired or
+    element-wise loads as above. Residual |PA - LU| against the componentwise
+    bound, computed in FP64 on the GPU; pivots in range."""
+    import torch
+
+    n = 8192
+    g = torch.Generator(device="cuda")
+    g.manual_seed(32)
+    a = (torch.rand(n, n, dtype=torch.float32, device="cuda", generator=g) * 2 - 1).double()
+    A = _dev_f32(a, n + ld_extra)
+    piv = ipiv_dev(n)
+    assert rl.sgetrf(A, piv, m=n, n=n, lda=n + ld_extra) == 0
+    ip = piv.cpu().numpy()[:n]
+    assert ((ip >= np.arange(1, n + 1)) & (ip <= n)).all()
+    perm = np.arange(n)
+    for k in range(n):
+        p = ip[k] - 1
+        perm[k], perm[p] = perm[p], perm[k]
+    f = A.double().contiguous()
+    L = torch.tril(f, -1) + torch.eye(n, dtype=torch.float64, device="cuda")
+    U = torch.triu(f)
+    assert float(L.abs().max()) <= 1.0
+    pa = a[torch.from_numpy(perm).cuda()]
+    res = float(torch.linalg.norm(pa - L @ U))
+    bound = 10 * n * U32 * float(torch.linalg.norm(L.abs() @ U.abs()))
+    assert res <= bound
