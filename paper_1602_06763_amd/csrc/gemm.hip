@@ -272,17 +272,20 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
         store_tiles(0);
         __syncthreads();
     }
-    // VEC (the 128-tile path): the next K tile goes to LDS right after the
-    // first quarter of the products (the other buffer was last read before the
-    // previous barrier), and the waves raise their issue priority while they
-    // feed the matrix cores. Measured at n = 4096 and 8192 against storing
-    // after the last quarter at normal priority with element-wise loads: from
-    // on par to 7 % faster, depending on the run.
-    constexpr int STORE_AFTER = VEC ? 0 : BK / 4 - 1;
+    // EARLY (paired loads on 128-tiles): the next K tile goes to LDS right
+    // after the first quarter of the products (the other buffer was last read
+    // before the previous barrier), and the waves raise their issue priority
+    // while they feed the matrix cores. Measured at n = 4096 and 8192 against
+    // storing after the last quarter at normal priority with element-wise
+    // loads: from on par to 7 % faster, depending on the run. On 64-tiles
+    // (four products per quarter and wave) it measured slower at n = 1024, so
+    // they take the paired loads alone (n = 1024 / 2048: 7 % faster).
+    constexpr bool EARLY = VEC && BM == 128;
+    constexpr int STORE_AFTER = EARLY ? 0 : BK / 4 - 1;
     for (long long kt = 0; kt < KT; ++kt) {
         const int buf = (int)(kt & 1);
         if (kt + 1 < KT) load_tiles((kt + 1) * BK);
-        if (VEC) __builtin_amdgcn_s_setprio(1);
+        if (EARLY) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
@@ -297,7 +300,7 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
                 for (int j = 0; j < NI; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
             if (ks == STORE_AFTER && kt + 1 < KT) store_tiles(buf ^ 1);
         }
-        if (VEC) __builtin_amdgcn_s_setprio(0);
+        if (EARLY) __builtin_amdgcn_s_setprio(0);
         __syncthreads();
     }
 
@@ -353,11 +356,16 @@ static bool pairs_aligned(const T *p, long long ld) {
 
 template <typename TL, typename TA, typename TB, typename TC, bool TRA, bool TRB, int TRI>
 static void dispatch_tile(Ctx &c, const GemmArgs<TA, TB, TC> &a) {
+    const bool pairs = pairs_aligned(a.A, a.lda) && pairs_aligned(a.B, a.ldb);
+    auto tile64 = [&](const GemmArgs<TA, TB, TC> &g, int ntiles) {
+        if (pairs) launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 64, true>(c, g, ntiles);
+        else launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 64, false>(c, g, ntiles);
+    };
     const long long big = ((a.m + 127) / 128) * ((a.n + 127) / 128) / (TRI ? 2 : 1);
     if (big >= 2LL * c.num_cu) {
         const int r = TRI ? tri_tail_tiles(c, a.m) : 0;
         const int T = (int)((a.m + 127) / 128), tiles = T * (T + 1) / 2;
-        if (pairs_aligned(a.A, a.lda) && pairs_aligned(a.B, a.ldb))
+        if (pairs)
             launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 128, true>(c, a, r > 0 ? tiles - r : -1);
         else
             launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 128, false>(c, a, r > 0 ? tiles - r : -1);
@@ -365,14 +373,14 @@ static void dispatch_tile(Ctx &c, const GemmArgs<TA, TB, TC> &a) {
             GemmArgs<TA, TB, TC> t = a;
             t.tail_T = T;
             t.tail_first = tiles - r;
-            launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 64>(c, t, 4 * r);
+            tile64(t, 4 * r);
         }
     } else if (TRI && ((a.m + 63) / 64) * ((a.m + 63) / 64 + 1) / 2 <= 4LL * c.num_cu) {
         // small triangular updates: 32-tiles give the chip four times the
         // workgroups (SYRK n = k = 1024: 88 -> 70 us; 512: 53 -> 35 us)
         launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 32>(c, a);
     } else {
-        launch_k1<TL, TA, TB, TC, TRA, TRB, TRI, 64>(c, a);
+        tile64(a, -1);
     }
 }
 
