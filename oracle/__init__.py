@@ -14,6 +14,9 @@ Parity status of each function (what pins it is in ``tests/test_oracle_pins.py``
 * ``getrf``            pinned: exact dyadic P·L·U, brute-force rationals
                        (n <= 6), Wilkinson ties, diagonal dominance,
                        permutation matrices, residual bound, zero pivots.
+* ``getrf_margin``     pinned: the same factorization as ``getrf`` bit for bit,
+                       Wilkinson ties (lead 0), the exact dyadic construction
+                       (lead >= 1/2), a hand-checked 3×3 column.
 * ``potrs``/``getrs``  pinned: exact solutions on the exact constructions,
                        residual bound on random inputs.
 * ``scale_spd_f32``/``scale_ge_f32`` pinned: powers of two, scaled ranges,
@@ -71,6 +74,8 @@ def lib() -> ctypes.CDLL:
         L.oracle_dpotrf.restype = c_int
         L.oracle_dgetrf.argtypes = [c_int, c_int, dp, c_int, ip]
         L.oracle_dgetrf.restype = c_int
+        L.oracle_dgetrf_margin.argtypes = [c_int, c_int, dp, c_int, ip, dp]
+        L.oracle_dgetrf_margin.restype = c_int
         L.oracle_dpotrs.argtypes = [c_char, c_int, c_int, dp, c_int, dp, c_int]
         L.oracle_dpotrs.restype = None
         L.oracle_dgetrs.argtypes = [c_char, c_int, c_int, dp, c_int, ip, dp, c_int]
@@ -133,6 +138,18 @@ def getrf(a):
     ipiv = np.zeros(max(min(m, n), 1), dtype=np.int32)
     info = lib().oracle_dgetrf(m, n, _dp(a), max(m, 1), _ip(ipiv))
     return a, ipiv[: min(m, n)], int(info)
+
+
+def getrf_margin(a):
+    """As ``getrf``, also returning each step's pivot lead over the runner-up,
+    (|a_pk| - max_{i != p} |a_ik|) / |a_pk|: (LU, ipiv, info, margin)."""
+    a = _f64(a)
+    m, n = a.shape
+    k = max(min(m, n), 1)
+    ipiv = np.zeros(k, dtype=np.int32)
+    margin = np.zeros(k)
+    info = lib().oracle_dgetrf_margin(m, n, _dp(a), max(m, 1), _ip(ipiv), _dp(margin))
+    return a, ipiv[: min(m, n)], int(info), margin[: min(m, n)]
 
 
 def potrs(fac, b, uplo: str = "L"):

@@ -121,21 +121,26 @@ int oracle_dpotrf(char uplo, int n, double *A, int lda)
  *      scale (the factorization still runs to completion).
  *   4. a_ij -= a_ik·a_kj for every i > k, j > k.
  */
-int oracle_dgetrf(int m, int n, double *A, int lda, int *ipiv)
+static int gepp(int m, int n, double *A, int lda, int *ipiv, double *margin)
 {
     int info = 0;
     const int mn = m < n ? m : n;
     for (int k = 0; k < mn; ++k) {
         int p = k;
-        double best = -1.0;
+        double best = -1.0, second = -1.0;
         for (int i = k; i < m; ++i) {
             const double v = fabs(AT(A, lda, i, k));
             if (v > best) {
+                second = best;
                 best = v;
                 p = i;
+            } else if (v > second) {
+                second = v;
             }
         }
         ipiv[k] = p + 1;
+        /* diagnostic only: how far the winner is ahead of the runner-up */
+        if (margin) margin[k] = best > 0.0 ? (best - (second > 0.0 ? second : 0.0)) / best : 0.0;
         if (AT(A, lda, p, k) != 0.0) {
             if (p != k) {
                 for (int j = 0; j < n; ++j) {
@@ -159,6 +164,24 @@ int oracle_dgetrf(int m, int n, double *A, int lda, int *ipiv)
         }
     }
     return info;
+}
+
+int oracle_dgetrf(int m, int n, double *A, int lda, int *ipiv)
+{
+    return gepp(m, n, A, lda, ipiv, NULL);
+}
+
+/*
+ * The same elimination, also reporting for every step k the pivot's relative
+ * lead over the runner-up, margin[k] = (|a_pk| - max_{i != p} |a_ik|) / |a_pk|
+ * (0 when the column is all zero). A floating-point implementation that
+ * rounds differently can legitimately choose another row only where this
+ * lead is within rounding of zero (a near-tie), so a pivot mismatch at a step
+ * with a clear lead is an error and one at a near-tie is not.
+ */
+int oracle_dgetrf_margin(int m, int n, double *A, int lda, int *ipiv, double *margin)
+{
+    return gepp(m, n, A, lda, ipiv, margin);
 }
 
 /*

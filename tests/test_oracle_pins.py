@@ -151,6 +151,31 @@ def test_lu_wilkinson_ties(orc, n):
     assert np.array_equal(np.diag(U)[:-1], np.ones(n - 1))
 
 
+def test_lu_margin_pins(orc):
+    """The pivot lead reported for the near-tie triage: every Wilkinson pivot is
+    an exact tie (lead 0, the last step has no rival: lead 1); on the exact
+    dyadic construction the pivot's multiplier is 1 and every other one at most
+    1/2 (lead >= 1/2); a hand-checked 3x3 first column (3, -2, 1) gives 1/3;
+    and the factorization itself is the plain oracle's, bit for bit."""
+    n = 40
+    lu, ipiv, info, margin = orc.getrf_margin(gen.wilkinson(n))
+    assert info == 0 and np.array_equal(ipiv, np.arange(1, n + 1))
+    assert np.array_equal(margin, np.r_[np.zeros(n - 1), 1.0])
+    a, perm, _, _ = gen.exact_lu(60, 60, seed=3)
+    lu, ipiv, info, margin = orc.getrf_margin(a)
+    assert (margin >= 0.5).all()
+    ref, rpiv, rinfo = orc.getrf(a)
+    assert np.array_equal(lu, ref) and np.array_equal(ipiv, rpiv) and info == rinfo
+    h = np.asfortranarray([[3.0, 1.0, 0.0], [-2.0, 4.0, 1.0], [1.0, 0.0, 5.0]])
+    _, ipiv, _, margin = orc.getrf_margin(h)
+    assert ipiv[0] == 1 and margin[0] == (3.0 - 2.0) / 3.0
+    g = gen.general_uniform(257, 190, seed=9)
+    lu, ipiv, info, margin = orc.getrf_margin(g)
+    ref, rpiv, rinfo = orc.getrf(g)
+    assert np.array_equal(lu, ref) and np.array_equal(ipiv, rpiv)
+    assert ((margin > 0) & (margin <= 1)).all()
+
+
 def test_lu_diag_dominant_no_interchange(orc):
     n = 300
     lu, ipiv, info = orc.getrf(gen.diag_dominant(n, seed=5))
