@@ -76,6 +76,14 @@ void relapack_dpotrf(char uplo, int n, double *A, int lda, int *info);
  * (a NaN never wins).
  * info = k > 0: U(k,k) is exactly zero (the first such k); the factorization
  * is completed.
+ * Limits: every leaf panel (at most 32 columns over all rows below its
+ * diagonal) runs as ceil(rows / 512) cooperating workgroups, one per CU, that
+ * wait on each other, so m <= 512·(number of CUs) = 131072 on MI355X. Before
+ * each panel the library checks that the kernel's occupancy lets the chip
+ * hold all of them at once (else info = -1000 - hipErrorCooperativeLaunchTooLarge
+ * and that panel is not launched). Every wait is bounded: if other work on the
+ * GPU keeps some of them from starting for about a second, the call returns
+ * info <= -2000 and A and ipiv are unusable.
  * Errors: m -1, n -2, lda -4.
  */
 void relapack_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info);
@@ -106,7 +114,10 @@ void relapack_dgetrs(char trans, int n, int nrhs, const double *A, int lda, cons
  * and the correction solve. Stops when every column's normwise backward error
  * eta = ||r||inf / (||A||inf·||x||inf + ||b||inf) <= 1e-14.
  * iter (host): > 0 refinement sweeps used; < 0 the FP64 path was used
- * instead: -3 the low-precision factorization failed, -31 no convergence.
+ * instead: -2 a value overflowed when rounded to the low precision (a scaled
+ * entry beyond the FP32 range, or a matrix-core operand beyond the FP16/BF16
+ * range during the factorization), -3 the low-precision factorization failed,
+ * -31 no convergence.
  * berr (host): the final max_j eta_j, computed in FP64.
  * Errors: uplo -1, n -2, nrhs -3, lda -5, ldb -7, ldx -9, prec -10.
  */

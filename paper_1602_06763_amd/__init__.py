@@ -6,6 +6,13 @@ device pointers: either raw integers or torch CUDA tensors (their
 ``data_ptr()``), column-major, i.e. a tensor ``t`` whose ``t.T`` is
 contiguous (``t.stride() == (1, ld)``). Nothing here computes: there is no
 CPU fallback, and loading fails loudly if the library has not been built.
+
+Tensor arguments are checked before anything reaches the library: each must
+be a CUDA tensor of the routine's dtype (float64 for the ``d`` routines,
+float32 for the ``s`` ones, int32 pivots and per-matrix sizes, int64 arrays
+of addresses) whose storage covers the column-major extent the call will
+touch, ``ld·(cols − 1) + rows`` elements from its start; a ValueError is
+raised otherwise. Raw integer addresses are passed through unchecked.
 """
 from __future__ import annotations
 
@@ -99,6 +106,40 @@ def _ptr(x) -> int:
     return int(x.data_ptr())
 
 
+_F64, _F32, _I32, _I64 = "float64", "float32", "int32", "int64"
+
+
+def _check(t, dtype: str, rows: int, cols: int, ld: int | None = None, what: str = "matrix") -> None:
+    """Refuse a tensor the kernels would read or write out of bounds: it must
+    be a CUDA tensor of ``dtype`` whose storage holds a column-major rows×cols
+    array with leading dimension ``ld`` starting at its data pointer. Raw
+    integer addresses and illegal sizes (which the library itself rejects
+    through info) pass unchecked."""
+    if t is None or isinstance(t, int):
+        return
+    if rows <= 0 or cols <= 0:
+        return
+    ld = rows if ld is None else ld
+    if ld < rows:
+        return   # the library reports the illegal leading dimension
+    if not t.is_cuda:
+        raise ValueError(f"{what}: expected a CUDA tensor, got one on {t.device}")
+    if str(t.dtype).replace("torch.", "") != dtype:
+        raise ValueError(f"{what}: expected dtype {dtype}, got {t.dtype}")
+    item = t.element_size()
+    start = t.storage_offset()
+    need = start + (cols - 1) * ld + rows
+    have = t.untyped_storage().nbytes() // item
+    if need > have:
+        raise ValueError(f"{what}: a {rows}x{cols} array with leading dimension {ld} needs {need} "
+                         f"elements of storage from the tensor's start, it has {have}")
+
+
+def _check_vec(t, dtype: str, count: int, what: str) -> None:
+    """A CUDA vector of ``dtype`` with at least ``count`` elements of storage."""
+    _check(t, dtype, count, 1, count, what)
+
+
 def _ld(t, rows):
     """Leading dimension of a column-major tensor (stride(0) == 1)."""
     if isinstance(t, int):
@@ -142,6 +183,7 @@ def finalize() -> None:
 def potrf(A, uplo: str = "L", n: int | None = None, lda: int | None = None) -> int:
     n = A.shape[0] if n is None else n
     lda = _ld(A, n) if lda is None else lda
+    _check(A, _F64, n, n, lda, "A")
     info = ctypes.c_int(0)
     lib().relapack_dpotrf(_b(uplo), n, _ptr(A), lda, ctypes.byref(info))
     return info.value
@@ -151,6 +193,8 @@ def getrf(A, ipiv, m: int | None = None, n: int | None = None, lda: int | None =
     m = A.shape[0] if m is None else m
     n = A.shape[1] if n is None else n
     lda = _ld(A, m) if lda is None else lda
+    _check(A, _F64, m, n, lda, "A")
+    _check_vec(ipiv, _I32, min(m, n), "ipiv")
     info = ctypes.c_int(0)
     lib().relapack_dgetrf(m, n, _ptr(A), lda, _ptr(ipiv), ctypes.byref(info))
     return info.value
@@ -158,6 +202,8 @@ def getrf(A, ipiv, m: int | None = None, n: int | None = None, lda: int | None =
 
 def potrs(A, B, uplo: str = "L") -> int:
     n, nrhs = B.shape[0], (B.shape[1] if B.dim() > 1 else 1)
+    _check(A, _F64, n, n, _ld(A, n), "A")
+    _check(B, _F64, n, nrhs, _ld(B, n), "B")
     info = ctypes.c_int(0)
     lib().relapack_dpotrs(_b(uplo), n, nrhs, _ptr(A), _ld(A, n), _ptr(B), _ld(B, n), ctypes.byref(info))
     return info.value
@@ -165,6 +211,9 @@ def potrs(A, B, uplo: str = "L") -> int:
 
 def getrs(A, ipiv, B, trans: str = "N") -> int:
     n, nrhs = B.shape[0], (B.shape[1] if B.dim() > 1 else 1)
+    _check(A, _F64, n, n, _ld(A, n), "A")
+    _check_vec(ipiv, _I32, n, "ipiv")
+    _check(B, _F64, n, nrhs, _ld(B, n), "B")
     info = ctypes.c_int(0)
     lib().relapack_dgetrs(_b(trans), n, nrhs, _ptr(A), _ld(A, n), _ptr(ipiv), _ptr(B), _ld(B, n),
                           ctypes.byref(info))
@@ -173,6 +222,9 @@ def getrs(A, ipiv, B, trans: str = "N") -> int:
 
 def posv_mixed(A, B, X, uplo: str = "L", prec=16):
     n, nrhs = B.shape[0], (B.shape[1] if B.dim() > 1 else 1)
+    _check(A, _F64, n, n, _ld(A, n), "A")
+    _check(B, _F64, n, nrhs, _ld(B, n), "B")
+    _check(X, _F64, n, nrhs, _ld(X, n), "X")
     it, berr, info = ctypes.c_int(0), ctypes.c_double(0.0), ctypes.c_int(0)
     lib().relapack_dposv_mixed(_b(uplo), n, nrhs, _ptr(A), _ld(A, n), _ptr(B), _ld(B, n), _ptr(X),
                                _ld(X, n), PREC.get(prec, prec), ctypes.byref(it), ctypes.byref(berr),
@@ -182,6 +234,10 @@ def posv_mixed(A, B, X, uplo: str = "L", prec=16):
 
 def gesv_mixed(A, ipiv, B, X, prec=16):
     n, nrhs = B.shape[0], (B.shape[1] if B.dim() > 1 else 1)
+    _check(A, _F64, n, n, _ld(A, n), "A")
+    _check_vec(ipiv, _I32, n, "ipiv")
+    _check(B, _F64, n, nrhs, _ld(B, n), "B")
+    _check(X, _F64, n, nrhs, _ld(X, n), "X")
     it, berr, info = ctypes.c_int(0), ctypes.c_double(0.0), ctypes.c_int(0)
     lib().relapack_dgesv_mixed(n, nrhs, _ptr(A), _ld(A, n), _ptr(ipiv), _ptr(B), _ld(B, n), _ptr(X),
                                _ld(X, n), PREC.get(prec, prec), ctypes.byref(it), ctypes.byref(berr),
@@ -190,6 +246,11 @@ def gesv_mixed(A, ipiv, B, X, prec=16):
 
 
 def gemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc) -> int:
+    ta, tb = str(transa).upper() == "T", str(transb).upper() == "T"
+    if k > 0:
+        _check(A, _F64, k if ta else m, m if ta else k, lda, "A")
+        _check(B, _F64, n if tb else k, k if tb else n, ldb, "B")
+    _check(C, _F64, m, n, ldc, "C")
     info = ctypes.c_int(0)
     lib().relapack_dgemm(_b(transa), _b(transb), m, n, k, alpha, _ptr(A), lda, _ptr(B), ldb, beta,
                          _ptr(C), ldc, ctypes.byref(info))
@@ -197,6 +258,10 @@ def gemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc) -> int:
 
 
 def syrk(uplo, trans, n, k, alpha, A, lda, beta, C, ldc) -> int:
+    tr = str(trans).upper() == "T"
+    if k > 0:
+        _check(A, _F64, k if tr else n, n if tr else k, lda, "A")
+    _check(C, _F64, n, n, ldc, "C")
     info = ctypes.c_int(0)
     lib().relapack_dsyrk(_b(uplo), _b(trans), n, k, alpha, _ptr(A), lda, beta, _ptr(C), ldc,
                          ctypes.byref(info))
@@ -204,6 +269,10 @@ def syrk(uplo, trans, n, k, alpha, A, lda, beta, C, ldc) -> int:
 
 
 def trsm(side, uplo, transa, diag, m, n, A, lda, B, ldb) -> int:
+    t = m if str(side).upper() == "L" else n
+    if m > 0 and n > 0:
+        _check(A, _F64, t, t, lda, "A")
+    _check(B, _F64, m, n, ldb, "B")
     info = ctypes.c_int(0)
     lib().relapack_dtrsm(_b(side), _b(uplo), _b(transa), _b(diag), m, n, _ptr(A), lda, _ptr(B), ldb,
                          ctypes.byref(info))
@@ -211,6 +280,10 @@ def trsm(side, uplo, transa, diag, m, n, A, lda, B, ldb) -> int:
 
 
 def trmm(side, uplo, transa, diag, m, n, alpha, A, lda, B, ldb) -> int:
+    t = m if str(side).upper() == "L" else n
+    if m > 0 and n > 0:
+        _check(A, _F64, t, t, lda, "A")
+    _check(B, _F64, m, n, ldb, "B")
     info = ctypes.c_int(0)
     lib().relapack_dtrmm(_b(side), _b(uplo), _b(transa), _b(diag), m, n, alpha, _ptr(A), lda, _ptr(B), ldb,
                          ctypes.byref(info))
@@ -219,28 +292,36 @@ def trmm(side, uplo, transa, diag, m, n, alpha, A, lda, B, ldb) -> int:
 
 def trtri(A, uplo: str = "L", diag: str = "N", n: int | None = None, lda: int | None = None) -> int:
     n = A.shape[0] if n is None else n
+    lda = _ld(A, n) if lda is None else lda
+    _check(A, _F64, n, n, lda, "A")
     info = ctypes.c_int(0)
-    lib().relapack_dtrtri(_b(uplo), _b(diag), n, _ptr(A), _ld(A, n) if lda is None else lda,
-                          ctypes.byref(info))
+    lib().relapack_dtrtri(_b(uplo), _b(diag), n, _ptr(A), lda, ctypes.byref(info))
     return info.value
 
 
 def lauum(A, uplo: str = "L", n: int | None = None, lda: int | None = None) -> int:
     n = A.shape[0] if n is None else n
+    lda = _ld(A, n) if lda is None else lda
+    _check(A, _F64, n, n, lda, "A")
     info = ctypes.c_int(0)
-    lib().relapack_dlauum(_b(uplo), n, _ptr(A), _ld(A, n) if lda is None else lda, ctypes.byref(info))
+    lib().relapack_dlauum(_b(uplo), n, _ptr(A), lda, ctypes.byref(info))
     return info.value
 
 
 def potri(A, uplo: str = "L", n: int | None = None, lda: int | None = None) -> int:
     n = A.shape[0] if n is None else n
+    lda = _ld(A, n) if lda is None else lda
+    _check(A, _F64, n, n, lda, "A")
     info = ctypes.c_int(0)
-    lib().relapack_dpotri(_b(uplo), n, _ptr(A), _ld(A, n) if lda is None else lda, ctypes.byref(info))
+    lib().relapack_dpotri(_b(uplo), n, _ptr(A), lda, ctypes.byref(info))
     return info.value
 
 
 def scale_spd_f32(A, d, S, uplo: str = "L") -> int:
     n = A.shape[0]
+    _check(A, _F64, n, n, _ld(A, n), "A")
+    _check_vec(d, _F64, n, "d")
+    _check(S, _F32, n, n, _ld(S, n), "S")
     info = ctypes.c_int(0)
     lib().relapack_scale_spd_f32(_b(uplo), n, _ptr(A), _ld(A, n), _ptr(d), _ptr(S), _ld(S, n),
                                  ctypes.byref(info))
@@ -249,6 +330,10 @@ def scale_spd_f32(A, d, S, uplo: str = "L") -> int:
 
 def scale_ge_f32(A, r, c, S) -> int:
     n = A.shape[0]
+    _check(A, _F64, n, n, _ld(A, n), "A")
+    _check_vec(r, _F64, n, "r")
+    _check_vec(c, _F64, n, "c")
+    _check(S, _F32, n, n, _ld(S, n), "S")
     info = ctypes.c_int(0)
     lib().relapack_scale_ge_f32(n, _ptr(A), _ld(A, n), _ptr(r), _ptr(c), _ptr(S), _ld(S, n),
                                 ctypes.byref(info))
@@ -257,6 +342,7 @@ def scale_ge_f32(A, r, c, S) -> int:
 
 def spotrf_lp(A, uplo: str = "L", prec=32) -> int:
     n = A.shape[0]
+    _check(A, _F32, n, n, _ld(A, n), "A")
     info = ctypes.c_int(0)
     lib().relapack_spotrf_lp(_b(uplo), n, _ptr(A), _ld(A, n), PREC.get(prec, prec), ctypes.byref(info))
     return info.value
@@ -264,6 +350,8 @@ def spotrf_lp(A, uplo: str = "L", prec=32) -> int:
 
 def sgetrf_lp(A, ipiv, prec=32) -> int:
     m, n = A.shape
+    _check(A, _F32, m, n, _ld(A, m), "A")
+    _check_vec(ipiv, _I32, min(m, n), "ipiv")
     info = ctypes.c_int(0)
     lib().relapack_sgetrf_lp(m, n, _ptr(A), _ld(A, m), _ptr(ipiv), PREC.get(prec, prec),
                              ctypes.byref(info))
@@ -272,20 +360,27 @@ def sgetrf_lp(A, ipiv, prec=32) -> int:
 
 def spotrf(A, uplo: str = "L", n: int | None = None, lda: int | None = None) -> int:
     n = A.shape[0] if n is None else n
+    lda = _ld(A, n) if lda is None else lda
+    _check(A, _F32, n, n, lda, "A")
     info = ctypes.c_int(0)
-    lib().relapack_spotrf(_b(uplo), n, _ptr(A), _ld(A, n) if lda is None else lda, ctypes.byref(info))
+    lib().relapack_spotrf(_b(uplo), n, _ptr(A), lda, ctypes.byref(info))
     return info.value
 
 
 def potrf_batched(uplo: str, count: int, n, A_ptrs, lda, info, single: bool = False) -> int:
     """Batched Cholesky: n, lda, info are device int32 arrays, A_ptrs a device int64 array of matrix
     addresses (count entries each). Returns the call status; per-matrix info lands in `info`."""
+    for t, dt, what in ((n, _I32, "n"), (A_ptrs, _I64, "A_ptrs"), (lda, _I32, "lda"), (info, _I32, "info")):
+        _check_vec(t, dt, count, what)
     f = lib().relapack_spotrf_batched if single else lib().relapack_dpotrf_batched
     return f(_b(uplo), count, _ptr(n), _ptr(A_ptrs), _ptr(lda), _ptr(info))
 
 
 def getrf_batched(count: int, n, A_ptrs, lda, ipiv_ptrs, info, single: bool = False) -> int:
     """Batched LU: as potrf_batched, with ipiv_ptrs a device int64 array of int32 pivot-array addresses."""
+    for t, dt, what in ((n, _I32, "n"), (A_ptrs, _I64, "A_ptrs"), (lda, _I32, "lda"),
+                        (ipiv_ptrs, _I64, "ipiv_ptrs"), (info, _I32, "info")):
+        _check_vec(t, dt, count, what)
     f = lib().relapack_sgetrf_batched if single else lib().relapack_dgetrf_batched
     return f(count, _ptr(n), _ptr(A_ptrs), _ptr(lda), _ptr(ipiv_ptrs), _ptr(info))
 
@@ -293,8 +388,11 @@ def getrf_batched(count: int, n, A_ptrs, lda, ipiv_ptrs, info, single: bool = Fa
 def sgetrf(A, ipiv, m: int | None = None, n: int | None = None, lda: int | None = None) -> int:
     m = A.shape[0] if m is None else m
     n = A.shape[1] if n is None else n
+    lda = _ld(A, m) if lda is None else lda
+    _check(A, _F32, m, n, lda, "A")
+    _check_vec(ipiv, _I32, min(m, n), "ipiv")
     info = ctypes.c_int(0)
-    lib().relapack_sgetrf(m, n, _ptr(A), _ld(A, m) if lda is None else lda, _ptr(ipiv), ctypes.byref(info))
+    lib().relapack_sgetrf(m, n, _ptr(A), lda, _ptr(ipiv), ctypes.byref(info))
     return info.value
 
 

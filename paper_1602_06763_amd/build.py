@@ -39,6 +39,11 @@ def build(verbose: bool = False) -> str:
     objs = []
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
+    # objects of sources that no longer exist are never linked; drop them
+    live = {os.path.basename(src) + ".o" for src in sources()}
+    for name in os.listdir(obj_dir):
+        if name.endswith(".o") and name not in live:
+            os.remove(os.path.join(obj_dir, name))
     procs = []
     for src in sources():
         obj = os.path.join(obj_dir, os.path.basename(src) + ".o")

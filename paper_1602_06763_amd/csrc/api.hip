@@ -69,7 +69,7 @@ __global__ void zero_u64_one_k(unsigned long long *p) {
 }
 
 __global__ void reset_status_k(DevStatus *s) {
-    if (threadIdx.x == 0) { s->info = 0; s->error = 0; s->barrier = 0u; s->pad = 0; }
+    if (threadIdx.x == 0) { s->info = 0; s->error = 0; s->barrier = 0u; s->ovf = 0; }
 }
 
 }  // namespace

@@ -44,7 +44,7 @@ struct DevStatus {
     int info;       // LAPACK info (first failing column, 1-based), 0 = fine
     int error;      // internal failure (e.g. a bounded wait that expired)
     unsigned int barrier;  // reserved
-    int pad;
+    int ovf;        // a value overflowed when rounded to a lower precision (mixed solves)
 };
 
 // One recorded kernel call (plan mode and the per-family timers).

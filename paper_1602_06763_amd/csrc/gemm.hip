@@ -62,6 +62,7 @@ struct GemmArgs {
     long long ldc;
     int tiles_m, tiles_n, ntiles;
     const int *abort;  // non-null: skip all work when *abort != 0
+    int *ovf;          // half-precision operands: set to 1 when one rounds to infinity
     // Triangular tail: when tail_T > 0 the launch covers, with tiles of half
     // the edge, the parent tiles tail_first.. of the band enumeration of a
     // tail_T-tile triangle (four quarters per parent, consecutive).
@@ -501,18 +502,25 @@ __global__ __launch_bounds__(256) void gemm_k8(GemmArgs<float, float, float> g) 
             rb[i] = in ? v : 0.f;
         }
     };
+    // an operand too large for the 16-bit format rounds to infinity: noted
+    // once per thread and reported at the end (the solve falls back to FP64)
+    bool inf_seen = false;
     auto store_tiles = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < EA; ++i) {
             int r, kk;
             a_coord(i, r, kk);
-            As[buf][r][kk] = (H)ra[i];
+            const H h = (H)ra[i];
+            inf_seen |= __builtin_isinf((float)h);
+            As[buf][r][kk] = h;
         }
 #pragma unroll
         for (int i = 0; i < EB; ++i) {
             int c, kk;
             b_coord(i, c, kk);
-            Bs[buf][c][kk] = (H)rb[i];
+            const H h = (H)rb[i];
+            inf_seen |= __builtin_isinf((float)h);
+            Bs[buf][c][kk] = h;
         }
     };
 
@@ -545,6 +553,7 @@ __global__ __launch_bounds__(256) void gemm_k8(GemmArgs<float, float, float> g) 
         __syncthreads();
     }
 
+    if (inf_seen && g.ovf) __hip_atomic_store(g.ovf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const float alpha = (float)g.alpha, beta = (float)g.beta;
     float *__restrict__ C = g.C;
 #pragma unroll
@@ -616,6 +625,7 @@ void gemm(Ctx &c, Mfma mode, char ta, char tb, char tri, long long m, long long 
     a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc;
     a.abort = c.dstat ? &c.dstat->info : nullptr;
     if (!c.abort_on_info) a.abort = nullptr;
+    a.ovf = c.dstat ? &c.dstat->ovf : nullptr;
     // the launch below picks 128×128 tiles exactly when this holds
     const bool big = ((m + 127) / 128) * ((n + 127) / 128) / (tri ? 2 : 1) >= 2LL * c.num_cu;
     const int kind = mode == Mfma::F64 ? (tri ? PK_SYRK : (big ? PK_GEMM_BIG : PK_GEMM))

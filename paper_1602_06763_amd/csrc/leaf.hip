@@ -468,11 +468,21 @@ void getf2_panel(Ctx &c, long long m, int w, T *A, long long lda, long long c0, 
     if (!a.rec) return;
     const size_t shm = (size_t)kPanelRows * kPanelLds * sizeof(T);
     static size_t attr_bytes = 0;
+    static int per_cu = -1;   // workgroups of this kernel one CU can hold
     if (shm > attr_bytes) {
         RL_CHECK(hipFuncSetAttribute((const void *)getf2_panel_k<T>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
         attr_bytes = shm;
+        per_cu = -1;
     }
+    if (per_cu < 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, getf2_panel_k<T>, 256, shm) != hipSuccess) nb = 0;
+        per_cu = nb;
+    }
+    // the workgroups wait on each other: refuse a launch the chip cannot hold
+    // at once instead of letting the bounded waits expire
+    if ((long long)per_cu * c.num_cu < G) { launch_error(hipErrorCooperativeLaunchTooLarge); return; }
     trace_kernel_begin(c);
     rl_launch(c, getf2_panel_k<T>, dim3(G), dim3(256), (unsigned)shm, A, a);
     RL_CHECK(hipGetLastError());

@@ -18,7 +18,7 @@ namespace rl {
 enum ScratchSlot { SL_LP = 0, SL_FULL = 1, SL_VEC = 2, SL_RED = 3, SL_FB = 4, SL_PIV = 5, SL_PERM = 6, SL_DINV = 8 };
 
 __global__ void reset_info_k(DevStatus *s) {
-    if (threadIdx.x == 0) { s->info = 0; s->error = 0; s->barrier = 0u; }
+    if (threadIdx.x == 0) { s->info = 0; s->error = 0; s->barrier = 0u; s->ovf = 0; }
 }
 
 __global__ void zero_u64_k(long long n, unsigned long long *p) {
@@ -51,14 +51,22 @@ __global__ void spd_diag_scale_k(long long n, const double *A, long long lda, do
     if (i < n) d[i] = quarter_scale(A[i + i * lda]);
 }
 
+// A scaled entry that rounds to an infinite float (the FP32 range is
+// exceeded) marks the status block: the solve then falls back to FP64.
+__device__ __forceinline__ float to_f32_flag(double v, DevStatus *st) {
+    const float f = (float)v;
+    if (__builtin_isinf(f) && st) __hip_atomic_store(&st->ovf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return f;
+}
+
 __global__ void spd_convert_k(long long n, const double *__restrict__ A, long long lda,
                               const double *__restrict__ d, float *__restrict__ S, long long lds,
-                              int lower) {
+                              int lower, DevStatus *st) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long j = blockIdx.y;
     if (i >= n) return;
     if (lower ? (i < j) : (i > j)) return;
-    S[i + j * lds] = (float)((d[i] * A[i + j * lda]) * d[j]);
+    S[i + j * lds] = to_f32_flag((d[i] * A[i + j * lda]) * d[j], st);
 }
 
 // max |a_ij| over each row, 2-D tiles combined with an atomic max on the
@@ -108,11 +116,11 @@ __global__ void to_half_scale_k(long long n, const double *mx, double *s) {
 
 __global__ void ge_convert_k(long long n, const double *__restrict__ A, long long lda,
                              const double *__restrict__ r, const double *__restrict__ c,
-                             float *__restrict__ S, long long lds) {
+                             float *__restrict__ S, long long lds, DevStatus *st) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long j = blockIdx.y;
     if (i >= n) return;
-    S[i + j * lds] = (float)((r[i] * A[i + j * lda]) * c[j]);
+    S[i + j * lds] = to_f32_flag((r[i] * A[i + j * lda]) * c[j], st);
 }
 
 static inline unsigned blocks(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
@@ -123,7 +131,7 @@ void scale_spd_f32(Ctx &c, char uplo, long long n, const double *A, long long ld
     trace_begin(c, PK_CONVERT);
     hipLaunchKernelGGL(spd_diag_scale_k, dim3(blocks(n)), dim3(256), 0, c.stream, n, A, lda, d);
     hipLaunchKernelGGL(spd_convert_k, dim3(blocks(n), (unsigned)n), dim3(256), 0, c.stream, n, A, lda, d, S,
-                       lds, (int)(uplo == 'L' || uplo == 'l'));
+                       lds, (int)(uplo == 'L' || uplo == 'l'), c.dstat);
     RL_CHECK(hipGetLastError());
     trace_end(c, PK_CONVERT, 0.0, 6.0 * n * n);
 }
@@ -142,7 +150,7 @@ void scale_ge_f32(Ctx &c, long long n, const double *A, long long lda, double *r
                        (double *)bits);
     hipLaunchKernelGGL(to_half_scale_k, dim3(blocks(n)), dim3(256), 0, c.stream, n, (const double *)bits, cs);
     hipLaunchKernelGGL(ge_convert_k, dim3(blocks(n), (unsigned)n), dim3(256), 0, c.stream, n, A, lda, r, cs, S,
-                       lds);
+                       lds, c.dstat);
     RL_CHECK(hipGetLastError());
     trace_end(c, PK_CONVERT, 0.0, 14.0 * n * n);
 }
@@ -570,10 +578,12 @@ int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const 
         RL_CHECK(hipGetLastError());
     }
     const int lp_info = fetch_info(c);
-    int status = 0;  // 0 running, 1 converged, -3 lp failed, -31 stalled
+    const bool overflow = c.hstat->ovf != 0;   // set by the conversion or a half-precision operand
+    int status = 0;  // 0 running, 1 converged, -2 overflow, -3 lp failed, -31 stalled
     double eta = INFINITY;
     int sweeps = 0;
-    if (lp_info != 0) status = -3;
+    if (overflow) status = -2;
+    else if (lp_info != 0) status = -3;
 
     if (status == 0) {
         prepare_correction(c, spd, uplo, n, nrhs, w);

@@ -169,3 +169,61 @@ def test_getrf_plan_rectangular():
     assert sum(r[3] for r in wide if r[0] == 5) == 300
     # the columns beyond the square part get one unit-lower solve with L11
     assert any(r[0] == 2 for r in wide[-5:]) or any(r[0] == 3 for r in wide[-5:])
+
+
+class _FakeStorage:
+    def __init__(self, nbytes):
+        self._n = nbytes
+
+    def nbytes(self):
+        return self._n
+
+
+class _FakeCudaTensor:
+    """Just the attributes the binding's argument check reads (no GPU needed)."""
+
+    def __init__(self, dtype, elems, offset=0, item=8):
+        self.is_cuda = True
+        self.dtype = dtype
+        self.device = "cuda:0"
+        self._elems, self._off, self._item = elems, offset, item
+
+    def element_size(self):
+        return self._item
+
+    def storage_offset(self):
+        return self._off
+
+    def untyped_storage(self):
+        return _FakeStorage(self._elems * self._item)
+
+
+def test_binding_refuses_bad_tensors():
+    import torch
+
+    import paper_1602_06763_amd as rl
+
+    # a CPU tensor never reaches the library
+    with pytest.raises(ValueError, match="CUDA"):
+        rl._check(torch.zeros(4, 4, dtype=torch.float64), "float64", 4, 4, 4, "A")
+    # wrong dtype
+    with pytest.raises(ValueError, match="dtype"):
+        rl._check(_FakeCudaTensor("torch.float32", 16, item=4), "float64", 4, 4, 4, "A")
+    # storage too small for ld·(cols−1) + rows from the view's start
+    rl._check(_FakeCudaTensor("torch.float64", 6 * 7 + 5), "float64", 5, 8, 6, "A")
+    with pytest.raises(ValueError, match="storage"):
+        rl._check(_FakeCudaTensor("torch.float64", 6 * 7 + 4), "float64", 5, 8, 6, "A")
+    with pytest.raises(ValueError, match="storage"):
+        rl._check(_FakeCudaTensor("torch.float64", 6 * 7 + 5, offset=1), "float64", 5, 8, 6, "A")
+    # an int64 pivot vector is refused, int32 of the right length accepted
+    with pytest.raises(ValueError, match="dtype"):
+        rl._check_vec(_FakeCudaTensor("torch.int64", 10), "int32", 10, "ipiv")
+    rl._check_vec(_FakeCudaTensor("torch.int32", 10, item=4), "int32", 10, "ipiv")
+    with pytest.raises(ValueError, match="storage"):
+        rl._check_vec(_FakeCudaTensor("torch.int32", 9, item=4), "int32", 10, "ipiv")
+    # illegal sizes are left to the library's own info codes
+    rl._check(_FakeCudaTensor("torch.float32", 1, item=4), "float64", 5, 5, 3, "A")
+    rl._check(_FakeCudaTensor("torch.float32", 1, item=4), "float64", -1, 5, 3, "A")
+    # through a wrapper: a CPU tensor raises before any library call
+    with pytest.raises(ValueError):
+        rl.potrf(torch.zeros(4, 4, dtype=torch.float64).T, "L")

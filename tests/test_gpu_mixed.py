@@ -121,3 +121,28 @@ def test_mixed_upper_and_fallback(orc):
     bad[5, 5] = -100.0
     info, it, berr, x = _solve("spd", bad, b, 32)
     assert info == 6 and it == -3
+
+
+def test_mixed_overflow_falls_back(orc):
+    """iter = -2 (a value overflowed when rounded to the low precision): the
+    Wilkinson growth matrix keeps its row and column scalings at 1 and its LU
+    grows the last column to 2^(i-1), beyond FP16's range (65504) after 17
+    rows, so the first FP16 matrix-core update meets an infinite operand; the
+    FP64 path then solves the system. That growth also makes partial pivoting
+    itself unstable here (backward error about 2^39·u), so the fallback's
+    answer is held to the FP64 solve's own (dgetrf + dgetrs on the same input),
+    not to 1e-14. FP32 operands hold 2^39 and do not overflow."""
+    n = 40
+    a = gen.wilkinson(n)
+    x0 = gen.rng(5).standard_normal(size=(n, 2))
+    b = np.asfortranarray(a @ x0)
+    info, it, berr, x = _solve("general", a, b, "fp16")
+    assert info == 0 and it == -2
+    eta, _ = orc.backward_error(a, x, b)
+    t, piv, bt = to_dev(a), ipiv_dev(n), to_dev(b)
+    assert rl.getrf(t, piv) == 0 and rl.getrs(t, piv, bt) == 0
+    eta64, _ = orc.backward_error(a, to_host(bt), b)
+    assert eta <= 2 * eta64 + 1e-15, (eta, eta64)
+    assert abs(berr - eta) <= 0.5 * eta + 1e-16
+    info, it, berr, x = _solve("general", a, b, 32)
+    assert info == 0 and it != -2
