@@ -89,6 +89,23 @@ void relapack_dpotrf(char uplo, int n, double *A, int lda, int *info);
 void relapack_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info);
 
 /*
+ * relapack_dgetrf without any allocation, for callers that cannot allocate
+ * device memory while they run (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). Same operation, arguments, results
+ * and kernels as relapack_dgetrf; the caller still passes A and ipiv. Its
+ * workspace (status block, row bookkeeping, panel exchange records; about
+ * 8.6 MB) is a fixed device array of the library, one per GPU, held until the
+ * process ends; the call makes no hipMalloc, hipFree or other allocating call.
+ * Limit: m <= 32768 (else info = -1 and nothing is launched). Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (from
+ * several processes, or from threads that bypass the per-device call lock
+ * by using different library instances) race. Within one process the
+ * per-device call lock serializes them.
+ * Errors: m -1 (negative or above 32768), n -2, lda -4.
+ */
+void relapack_dgetrf_noalloc(int m, int n, double *A, int lda, int *ipiv, int *info);
+
+/*
  * Solve A·X = B with the factor from relapack_dpotrf (xpotrs). A: the n×n
  * factor; B: n×nrhs, overwritten by X.
  * Errors: uplo -1, n -2, nrhs -3, lda -5, ldb -7.

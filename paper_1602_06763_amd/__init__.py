@@ -38,6 +38,7 @@ _SIGS = {
     "relapack_finalize": ([], None),
     "relapack_dpotrf": ([_c_char, _c_int, _vp, _c_int, _ip], None),
     "relapack_dgetrf": ([_c_int, _c_int, _vp, _c_int, _vp, _ip], None),
+    "relapack_dgetrf_noalloc": ([_c_int, _c_int, _vp, _c_int, _vp, _ip], None),
     "relapack_dpotrs": ([_c_char, _c_int, _c_int, _vp, _c_int, _vp, _c_int, _ip], None),
     "relapack_dgetrs": ([_c_char, _c_int, _c_int, _vp, _c_int, _vp, _vp, _c_int, _ip], None),
     "relapack_dposv_mixed": ([_c_char, _c_int, _c_int, _vp, _c_int, _vp, _c_int, _vp, _c_int, _c_int,
@@ -197,6 +198,18 @@ def getrf(A, ipiv, m: int | None = None, n: int | None = None, lda: int | None =
     _check_vec(ipiv, _I32, min(m, n), "ipiv")
     info = ctypes.c_int(0)
     lib().relapack_dgetrf(m, n, _ptr(A), lda, _ptr(ipiv), ctypes.byref(info))
+    return info.value
+
+
+def getrf_noalloc(A, ipiv, m: int | None = None, n: int | None = None, lda: int | None = None) -> int:
+    """relapack_dgetrf_noalloc: the LU on the library's fixed workspace (m <= 32768)."""
+    m = A.shape[0] if m is None else m
+    n = A.shape[1] if n is None else n
+    lda = _ld(A, m) if lda is None else lda
+    _check(A, _F64, m, n, lda, "A")
+    _check_vec(ipiv, _I32, min(m, n), "ipiv")
+    info = ctypes.c_int(0)
+    lib().relapack_dgetrf_noalloc(m, n, _ptr(A), lda, _ptr(ipiv), ctypes.byref(info))
     return info.value
 
 

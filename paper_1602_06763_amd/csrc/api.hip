@@ -115,7 +115,13 @@ static void ensure_rowsrc(Ctx &c, size_t m) {
     c.rowsrc_elems = d.rowsrc_elems;
 }
 
-void *scratch(Ctx &c, int slot, size_t bytes) {
+void *workspace(Ctx &c, int slot, size_t bytes) {
+    if (c.fixed) {
+        // a caller-free call holds only the LU row tracker
+        if (slot == 7 && bytes <= c.fixed->tracker_bytes) return c.fixed->tracker;
+        launch_error(hipErrorOutOfMemory);
+        return nullptr;
+    }
     std::lock_guard<std::mutex> lk(g_mu);
     DevState &d = g_dev[c.device];
     if (d.slot_bytes[slot] < bytes) {
@@ -132,9 +138,21 @@ void *scratch(Ctx &c, int slot, size_t bytes) {
 }
 
 unsigned long long *panel_records(Ctx &c, unsigned int *epoch) {
+    const long long words = (long long)kLuLeaf * kRecSlots * kRecWords;
+    if (c.fixed) {
+        unsigned int &e = *c.fixed->epoch;
+        if (e < 2u * kLuLeaf || e > 0xFFFFFFFFu - 2u * kLuLeaf) {
+            hipLaunchKernelGGL(fill_u64_k, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, c.stream,
+                               c.fixed->rec, words, 0ull);
+            RL_CHECK(hipGetLastError());
+            e = 2u * kLuLeaf;
+        }
+        *epoch = e;
+        e += kLuLeaf;
+        return c.fixed->rec;
+    }
     std::lock_guard<std::mutex> lk(g_mu);
     DevState &d = g_dev[c.device];
-    const long long words = (long long)kLuLeaf * kRecSlots * kRecWords;
     if (!d.panel_rec) {
         if (hipMalloc(&d.panel_rec, (size_t)words * sizeof(unsigned long long)) != hipSuccess) {
             d.panel_rec = nullptr;
@@ -158,6 +176,10 @@ unsigned long long *panel_records(Ctx &c, unsigned int *epoch) {
 
 TrsvWork trsv_work(Ctx &c, long long m, int nb, int launches, long long row_words, int tickets_per_block) {
     TrsvWork w;
+    if (c.fixed) {   // never reached: caller-free calls take the recursive solves
+        launch_error(hipErrorOutOfMemory);
+        return w;
+    }
     std::lock_guard<std::mutex> lk(g_mu);
     DevState &d = g_dev[c.device];
     const long long words = m * row_words;
@@ -297,6 +319,99 @@ static int getrf_batched_call(int count, const int *n, T *const *A, const int *l
     return r < 0 ? r : 0;
 }
 
+// ---- allocation-free LU: fixed device workspace ------------------------------
+// relapack_dgetrf_noalloc runs on this array instead of the grow-only
+// workspace: status block, the source row of every position after a panel,
+// the row tracker (two buffers, the inverse slots, the batch source map) and
+// the panel exchange records, for at most kNaMaxM rows. Every GPU the library
+// runs on holds one copy (about 8.6 MB) until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns per device.
+constexpr long long kNaMaxM = kLaswpBatchRows;
+constexpr size_t kNaStatusOff = 0;
+constexpr size_t kNaRowsrcOff = 256;
+constexpr size_t kNaTrackerOff = kNaRowsrcOff + (size_t)kNaMaxM * sizeof(int);
+constexpr size_t kNaTrackerBytes = (size_t)(4 + 2 * kLaswpDepth) * (size_t)kNaMaxM * sizeof(int);
+constexpr size_t kNaRecOff = kNaTrackerOff + kNaTrackerBytes;
+constexpr size_t kNaRecBytes = (size_t)kLuLeaf * kRecSlots * kRecWords * sizeof(unsigned long long);
+constexpr size_t kNaBytes = kNaRecOff + kNaRecBytes;
+static_assert(kNaRecOff % 256 == 0, "records start on a 256-byte boundary");
+
+}  // namespace rl
+
+static __device__ __align__(256) unsigned char scratch[rl::kNaBytes];
+
+namespace rl {
+namespace {
+
+struct NaDev {
+    unsigned char *ptr = nullptr;   // this device's copy of `scratch`
+    int num_cu = 256;
+    unsigned int epoch = 0;         // next free epoch of its panel records
+    FixedWs ws;
+};
+NaDev g_na[kMaxDev];
+thread_local DevStatus t_na_status;   // host copy of the status block (pageable)
+
+// Device address of `scratch` on the current device, looked up once per
+// device; the call lock of that device is taken as for every other call.
+bool na_call_begin(Ctx &c) {
+    t_err = 0;
+    int dev = 0;
+    RL_CHECK(hipGetDevice(&dev));
+    if (t_err) return false;
+    if (dev < 0 || dev >= kMaxDev) { launch_error(hipErrorInvalidDevice); return false; }
+    NaDev &d = g_na[dev];
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!d.ptr) {
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) {
+                launch_error(e != hipSuccess ? e : hipErrorInvalidSymbol);
+                return false;
+            }
+            int cu = 0;
+            if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+                d.num_cu = cu;
+            unsigned char *b = (unsigned char *)p;
+            d.ws.tracker = (int *)(b + kNaTrackerOff);
+            d.ws.tracker_bytes = kNaTrackerBytes;
+            d.ws.rec = (unsigned long long *)(b + kNaRecOff);
+            d.ws.epoch = &d.epoch;
+            d.epoch = 0;   // the first panel clears the records
+            d.ptr = b;
+        }
+    }
+    if (t_locked < 0) {
+        g_call_mu[dev].lock();
+        t_locked = dev;
+    }
+    c.device = dev;
+    c.dstat = (DevStatus *)(d.ptr + kNaStatusOff);
+    c.hstat = &t_na_status;
+    c.rowsrc = (int *)(d.ptr + kNaRowsrcOff);
+    c.rowsrc_elems = (size_t)kNaMaxM;
+    c.num_cu = d.num_cu;
+    c.fixed = &d.ws;
+    c.abort_on_info = false;
+    c.level = 0;
+    hipLaunchKernelGGL(reset_status_k, dim3(1), dim3(64), 0, c.stream, c.dstat);
+    RL_CHECK(hipGetLastError());
+    return t_err == 0;
+}
+
+int na_call_end(Ctx &c) {
+    const int r = call_end(c);
+    c.fixed = nullptr;
+    c.dstat = nullptr;
+    c.hstat = nullptr;
+    c.rowsrc = nullptr;
+    c.rowsrc_elems = 0;
+    c.lu_tracked = false;
+    return r;
+}
+
+}  // namespace
 }  // namespace rl
 
 extern "C" {
@@ -359,6 +474,19 @@ void relapack_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info) {
     ensure_rowsrc(c, (size_t)m);
     getrf_top<double>(c, Mfma::F64, m, n, A, lda, ipiv);
     *info = call_end(c);
+}
+
+void relapack_dgetrf_noalloc(int m, int n, double *A, int lda, int *ipiv, int *info) {
+    if (!info) return;
+    if (m < 0 || m > kNaMaxM) { *info = -1; return; }
+    if (n < 0) { *info = -2; return; }
+    if (lda < (m > 1 ? m : 1)) { *info = -4; return; }
+    *info = 0;
+    if (m == 0 || n == 0) return;
+    Ctx &c = ctx();
+    if (!na_call_begin(c)) { *info = na_call_end(c); return; }
+    getrf_top<double>(c, Mfma::F64, m, n, A, lda, ipiv);
+    *info = na_call_end(c);
 }
 
 void relapack_dpotrs(char uplo, int n, int nrhs, const double *A, int lda, double *B, int ldb,

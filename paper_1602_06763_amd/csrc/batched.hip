@@ -495,7 +495,7 @@ template <int KMAX>
 static bool batch_order(Ctx &c, int count, const int *n, const int **perm) {
     *perm = nullptr;
     if (count <= 2 * c.num_cu) return true;
-    int *p = (int *)scratch(c, kSlotBatchOrder, (size_t)count * sizeof(int));
+    int *p = (int *)workspace(c, kSlotBatchOrder, (size_t)count * sizeof(int));
     if (!p) return false;
     rl_launch(c, batch_order_k<KMAX>, dim3(1), dim3(1024), 0, count, n, p);
     RL_CHECK(hipGetLastError());

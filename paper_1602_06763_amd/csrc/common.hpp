@@ -61,6 +61,17 @@ enum PlanKind : int {
     PK_TRTI2 = 13, PK_TRMM_LEAF = 14, PK_LAUU2 = 15
 };
 
+// Workspace that a caller-free entry point brings in from a fixed device
+// array instead of the library's grow-only allocations: the LU row tracker
+// (what workspace slot 7 holds otherwise) and the panel exchange records with
+// their own epoch counter. Nothing is allocated while it is set.
+struct FixedWs {
+    int *tracker = nullptr;
+    size_t tracker_bytes = 0;
+    unsigned long long *rec = nullptr;
+    unsigned int *epoch = nullptr;   // next free epoch of rec (host side, per device)
+};
+
 // Per-thread library state: stream, plan recording, tracing.
 struct Ctx {
     hipStream_t stream = nullptr;
@@ -88,11 +99,14 @@ struct Ctx {
     hipEvent_t tev0 = nullptr, tev1 = nullptr;   // armed pair for the next launch
     bool tev_armed = false, tev_used = false;
     int num_cu = 256;
+    // set only during a caller-free call: workspace comes from here, and the
+    // left-side solves avoid the single-launch TRSV (which needs its own buffers)
+    FixedWs *fixed = nullptr;
 };
 
 Ctx &ctx();
 void ensure_device(Ctx &c);
-void *scratch(Ctx &c, int slot, size_t bytes);   // grow-only per-device workspace
+void *workspace(Ctx &c, int slot, size_t bytes);   // grow-only per-device workspace
 constexpr int kSlotBatchOrder = 9;                 // workspace slot: launch order of a batch
 // Exchange records of the cooperative LU panel ([kLuLeaf][kRecSlots][kRecWords]
 // words) and the first of kLuLeaf consecutive epochs reserved for one panel.

@@ -103,7 +103,7 @@ void getrf_top(Ctx &c, Mfma mode, long long m, long long n, T *A, long long lda,
     c.lu_batch = mn > kLaswpBlock && m <= kLaswpBatchRows;
     if (c.lu_batch && !c.plan) {
         c.pv_m = m;
-        c.pv = (int *)scratch(c, 7, (size_t)(4 + 2 * kLaswpDepth) * (size_t)m * sizeof(int));
+        c.pv = (int *)workspace(c, 7, (size_t)(4 + 2 * kLaswpDepth) * (size_t)m * sizeof(int));
         c.pcur = 0;
         if (!c.pv) { c.lu_batch = false; return; }
     }

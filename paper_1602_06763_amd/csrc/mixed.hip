@@ -139,7 +139,7 @@ void scale_spd_f32(Ctx &c, char uplo, long long n, const double *A, long long ld
 void scale_ge_f32(Ctx &c, long long n, const double *A, long long lda, double *r, double *cs, float *S,
                   long long lds) {
     if (plan_record(c, PK_CONVERT, n, n, 0)) return;
-    unsigned long long *bits = (unsigned long long *)scratch(c, SL_RED, (size_t)n * 8);
+    unsigned long long *bits = (unsigned long long *)workspace(c, SL_RED, (size_t)n * 8);
     if (!bits) return;
     trace_begin(c, PK_CONVERT);
     hipLaunchKernelGGL(zero_u64_k, dim3(blocks(n)), dim3(256), 0, c.stream, n, bits);
@@ -509,7 +509,7 @@ static void correction(Ctx &c, bool spd, char uplo, long long n, long long nrhs,
 static void prepare_correction(Ctx &c, bool spd, char uplo, long long n, long long nrhs, MixedWork &w) {
     if (nrhs != 1 || n <= 2 * kTrsmLeaf) return;   // one right-hand side: the single-launch solve
     const long long nb = (n + 63) / 64;
-    double *d = (double *)scratch(c, SL_DINV, (size_t)2 * nb * 4096 * sizeof(double));
+    double *d = (double *)workspace(c, SL_DINV, (size_t)2 * nb * 4096 * sizeof(double));
     if (!d) return;
     w.dinv1 = d;
     w.dinv2 = d + nb * 4096;
@@ -532,14 +532,14 @@ int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const 
     const double tol = 1e-14;
     const int max_sweeps = 30;
     MixedWork w;
-    w.S = (float *)scratch(c, SL_LP, (size_t)n * n * sizeof(float));
+    w.S = (float *)workspace(c, SL_LP, (size_t)n * n * sizeof(float));
     w.ldaf = spd ? n : lda;
-    if (spd) w.Af = (double *)scratch(c, SL_FULL, (size_t)n * n * sizeof(double));
+    if (spd) w.Af = (double *)workspace(c, SL_FULL, (size_t)n * n * sizeof(double));
     else w.Af = const_cast<double *>(A);
     const long long nchunk = (n + 255) / 256;
     const size_t vec = (size_t)(2 * n + 2 * n * nrhs + nrhs + 2 + nchunk * n + blocks(n));
-    double *v = (double *)scratch(c, SL_VEC, vec * sizeof(double));
-    w.ipiv = spd ? nullptr : (ipiv_out ? ipiv_out : (int *)scratch(c, SL_PIV, (size_t)n * sizeof(int)));
+    double *v = (double *)workspace(c, SL_VEC, vec * sizeof(double));
+    w.ipiv = spd ? nullptr : (ipiv_out ? ipiv_out : (int *)workspace(c, SL_PIV, (size_t)n * sizeof(int)));
     if (!w.S || !w.Af || !v) return -1000 - (int)hipErrorOutOfMemory;
     w.s1 = v; w.s2 = v + n; w.R = v + 2 * n; w.D = w.R + n * nrhs; w.eta = w.D + n * nrhs;
     w.scal = w.eta + nrhs; w.part = w.scal + 2;
@@ -564,7 +564,7 @@ int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const 
         // the factorization's row tracker is the gather map itself
         w.perm = c.pv + (size_t)c.pcur * c.pv_m;
     } else if (!spd) {
-        w.perm = (int *)scratch(c, SL_PERM, (size_t)n * sizeof(int));
+        w.perm = (int *)workspace(c, SL_PERM, (size_t)n * sizeof(int));
         if (!w.perm) return -1000 - (int)hipErrorOutOfMemory;
         const size_t shm = n <= 16384 ? (size_t)2 * n * sizeof(int) : 0;
         static size_t attr = 0;
@@ -613,7 +613,7 @@ int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const 
         return 0;
     }
     // FP64 fallback on a copy of A (A itself is never modified)
-    double *F = (double *)scratch(c, SL_FB, (size_t)n * n * sizeof(double));
+    double *F = (double *)workspace(c, SL_FB, (size_t)n * n * sizeof(double));
     if (!F) return -1000 - (int)hipErrorOutOfMemory;
     hipLaunchKernelGGL(copy_cols_k, dim3(blocks(n), (unsigned)n), dim3(256), 0, c.stream, n, n, A, lda, F, n);
     hipLaunchKernelGGL(copy_cols_k, dim3(blocks(n), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs, B, ldb, X,

@@ -719,7 +719,7 @@ void trsm(Ctx &c, Mfma mode, char side, char uplo, char trans, char diag, long l
     const int top = leaf == kTrsmLeaf ? 2 * kTrsmLeaf : leaf;
     if (is(side, 'L')) {
         // op(T)·X = B, X m×n, triangle m×m
-        if (!c.plan && n <= kTrsvMaxRhs && m > top) {
+        if (!c.plan && !c.fixed && n <= kTrsvMaxRhs && m > top) {
             trsv<TT, TB>(c, lowerM, tr, unit, m, n, T, ldt, B, ldb, nullptr);
             return;
         }

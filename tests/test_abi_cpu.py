@@ -42,6 +42,12 @@ def test_argument_checks_without_gpu():
     assert _info(L.relapack_dgetrf, 4, -1, 0, 4, 0) == -2
     assert _info(L.relapack_dgetrf, 9, 4, 0, 8, 0) == -4
     assert _info(L.relapack_dgetrf, 0, 5, 0, 1, 0) == 0
+    # the allocation-free LU: same checks, and m above its fixed workspace (32768 rows) is refused
+    assert _info(L.relapack_dgetrf_noalloc, -1, 4, 0, 4, 0) == -1
+    assert _info(L.relapack_dgetrf_noalloc, 32769, 4, 0, 32769, 0) == -1
+    assert _info(L.relapack_dgetrf_noalloc, 4, -1, 0, 4, 0) == -2
+    assert _info(L.relapack_dgetrf_noalloc, 9, 4, 0, 8, 0) == -4
+    assert _info(L.relapack_dgetrf_noalloc, 0, 5, 0, 1, 0) == 0
     assert _info(L.relapack_dpotrs, b"Q", 4, 1, 0, 4, 0, 4) == -1
     assert _info(L.relapack_dpotrs, b"L", 4, -2, 0, 4, 0, 4) == -3
     assert _info(L.relapack_dpotrs, b"L", 4, 1, 0, 4, 0, 3) == -7
