@@ -433,9 +433,11 @@ def mixed_sweep(n: int, stream, reps: int = 2):
                         ms, r = timed(lambda: rl.posv_mixed(M, bb, X, "L", prec))
                     else:
                         ms, r = timed(lambda: rl.gesv_mixed(M, pv, bb, X, prec))
+                    st = rl.mixed_last()
                     rows.append({"kind": kind, "kappa": kappa, "nrhs": nrhs, "prec": prec, "ms": round(ms, 3),
                                  "fp64_solve_ms": round(fp64[nrhs], 3), "speedup": round(fp64[nrhs] / ms, 3),
-                                 "info": r[0], "iter": r[1], "berr": r[2]})
+                                 "info": r[0], "iter": r[1], "berr": r[2], "gmres_from": st["gmres_from"],
+                                 "gmres_steps": st["gmres_steps"]})
                 del X
             del M, b
             torch.cuda.empty_cache()

@@ -130,6 +130,16 @@ void relapack_dgetrs(char trans, int n, int nrhs, const double *A, int lda, cons
  * FP32 accumulation). FP64 is used for the residual r = b - A·x, the update
  * and the correction solve. Stops when every column's normwise backward error
  * eta = ||r||inf / (||A||inf·||x||inf + ||b||inf) <= 1e-14.
+ * Sweeps: plain refinement (x += M⁻¹r, M the scaled low-precision factors,
+ * applied in FP64) while each sweep cuts eta at least fourfold; after that
+ * GMRES-IR: each sweep solves A·d = r by FP64 GMRES left-preconditioned by
+ * M⁻¹ (restart 40, inner tolerance 1e-6, at most 200 Arnoldi steps per
+ * solve; Carson and Higham's GMRES-based refinement). Refinement stops after
+ * 30 sweeps, when eta fails twice to halve under GMRES-IR, or when a GMRES
+ * sweep's residual reduction over its first 12 steps, kept up, would not
+ * reach 1e-6 within the remaining Arnoldi budget (the preconditioned matrix
+ * then has too many scattered eigenvalues, as when kappa times the
+ * factorization's unit roundoff is well above 1).
  * iter (host): > 0 refinement sweeps used; < 0 the FP64 path was used
  * instead: -2 a value overflowed when rounded to the low precision (a scaled
  * entry beyond the FP32 range, or a matrix-core operand beyond the FP16/BF16
@@ -152,6 +162,13 @@ void relapack_dposv_mixed(char uplo, int n, int nrhs, const double *A, int lda, 
 void relapack_dgesv_mixed(int n, int nrhs, const double *A, int lda, int *ipiv, const double *B,
                           int ldb, double *X, int ldx, int prec, int *iter, double *berr,
                           int *info);
+
+/*
+ * What the calling thread's last mixed solve did: refinement sweeps in all,
+ * the sweep from which GMRES-IR ran (0: plain refinement throughout), the
+ * GMRES-IR sweeps and their Arnoldi steps. NULL pointers are skipped.
+ */
+void relapack_mixed_last(int *sweeps, int *gmres_from, int *gmres_sweeps, int *gmres_steps);
 
 /* ---- building blocks on the recursion's path (FP64 matrix cores) -------- */
 

@@ -45,6 +45,7 @@ _SIGS = {
                               _ip, _dp, _ip], None),
     "relapack_dgesv_mixed": ([_c_int, _c_int, _vp, _c_int, _vp, _vp, _c_int, _vp, _c_int, _c_int, _ip,
                               _dp, _ip], None),
+    "relapack_mixed_last": ([_ip, _ip, _ip, _ip], None),
     "relapack_dgemm": ([_c_char, _c_char, _c_int, _c_int, _c_int, _c_double, _vp, _c_int, _vp, _c_int,
                         _c_double, _vp, _c_int, _ip], None),
     "relapack_dsyrk": ([_c_char, _c_char, _c_int, _c_int, _c_double, _vp, _c_int, _c_double, _vp, _c_int,
@@ -256,6 +257,14 @@ def gesv_mixed(A, ipiv, B, X, prec=16):
                                _ld(X, n), PREC.get(prec, prec), ctypes.byref(it), ctypes.byref(berr),
                                ctypes.byref(info))
     return info.value, it.value, berr.value
+
+
+def mixed_last() -> dict:
+    """relapack_mixed_last: what the calling thread's last mixed solve did."""
+    v = [ctypes.c_int(0) for _ in range(4)]
+    lib().relapack_mixed_last(*[ctypes.byref(x) for x in v])
+    return {"sweeps": v[0].value, "gmres_from": v[1].value, "gmres_sweeps": v[2].value,
+            "gmres_steps": v[3].value}
 
 
 def gemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc) -> int:

@@ -13,8 +13,8 @@ namespace rl {
 namespace {
 
 constexpr int kMaxDev = 16;
-constexpr int kScratchSlots = 10;   // 0-6 mixed solver, 7 LU row tracker, 8 correction-solve block inverses,
-                                    // 9 launch order of a batch
+constexpr int kScratchSlots = 11;   // 0-6 mixed solver, 7 LU row tracker, 8 correction-solve block inverses,
+                                    // 9 launch order of a batch, 10 GMRES basis
 
 struct DevState {
     bool init = false;
@@ -638,6 +638,14 @@ void relapack_dposv_mixed(char uplo, int n, int nrhs, const double *A, int lda, 
     *info = e < 0 ? e : r;
     if (iter) *iter = it;
     if (berr) *berr = be;
+}
+
+void relapack_mixed_last(int *sweeps, int *gmres_from, int *gmres_sweeps, int *gmres_steps) {
+    const MixedStats st = mixed_last_stats();
+    if (sweeps) *sweeps = st.sweeps;
+    if (gmres_from) *gmres_from = st.switched_at;
+    if (gmres_sweeps) *gmres_sweeps = st.gmres_sweeps;
+    if (gmres_steps) *gmres_steps = st.gmres_steps;
 }
 
 void relapack_dgesv_mixed(int n, int nrhs, const double *A, int lda, int *ipiv, const double *B, int ldb,

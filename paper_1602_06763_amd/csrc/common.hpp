@@ -218,6 +218,14 @@ void scale_spd_f32(Ctx &c, char uplo, long long n, const double *A, long long ld
 void scale_ge_f32(Ctx &c, long long n, const double *A, long long lda, double *r, double *cs,
                   float *S, long long lds);
 
+// What the last mixed solve of the calling thread did: refinement sweeps in
+// all, the sweep from which GMRES-IR ran (0: plain refinement throughout), the
+// GMRES-IR sweeps and their Arnoldi steps, the final status (1 converged, -2,
+// -3, -31 as iter).
+struct MixedStats {
+    int sweeps = 0, switched_at = 0, gmres_sweeps = 0, gmres_steps = 0, status = 0;
+};
+MixedStats mixed_last_stats();
 int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const double *A, long long lda,
                 int *ipiv_out, const double *B, long long ldb, double *X, long long ldx, int prec, int *iter,
                 double *berr);

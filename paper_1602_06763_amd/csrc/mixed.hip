@@ -15,7 +15,8 @@
 
 namespace rl {
 
-enum ScratchSlot { SL_LP = 0, SL_FULL = 1, SL_VEC = 2, SL_RED = 3, SL_FB = 4, SL_PIV = 5, SL_PERM = 6, SL_DINV = 8 };
+enum ScratchSlot { SL_LP = 0, SL_FULL = 1, SL_VEC = 2, SL_RED = 3, SL_FB = 4, SL_PIV = 5, SL_PERM = 6, SL_DINV = 8,
+                  SL_GM = 10 };
 
 __global__ void reset_info_k(DevStatus *s) {
     if (threadIdx.x == 0) { s->info = 0; s->error = 0; s->barrier = 0u; s->ovf = 0; }
@@ -347,7 +348,7 @@ static Mfma prec_mode(int prec) {
 // every load of A is a coalesced 512-byte column segment; 16 columns are in
 // flight per wave.
 constexpr int kResidMaxRhs = 4;
-template <int NR>
+template <int NR, bool MV = false>
 __global__ __launch_bounds__(256) void resid_k(long long n, const double *__restrict__ A, long long lda,
                                                const double *__restrict__ X, long long ldx,
                                                const double *__restrict__ B, long long ldb, double *__restrict__ R,
@@ -382,7 +383,10 @@ __global__ __launch_bounds__(256) void resid_k(long long n, const double *__rest
     if (wave == 0 && row < n) {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-            R[row + r * ldr] = B[row + r * ldb] - ((part[0][r][lane] + part[1][r][lane]) + (part[2][r][lane] + part[3][r][lane]));
+        {
+            const double ax = (part[0][r][lane] + part[1][r][lane]) + (part[2][r][lane] + part[3][r][lane]);
+            R[row + r * ldr] = MV ? ax : B[row + r * ldb] - ax;
+        }
     }
 }
 
@@ -525,12 +529,275 @@ static void prepare_correction(Ctx &c, bool spd, char uplo, long long n, long lo
     }
 }
 
+// ---- GMRES-IR ----------------------------------------------------------------
+// When plain refinement contracts slowly (kappa·u_f near or above 1), each
+// sweep instead solves the correction equation A·d = r with FP64 GMRES, left
+// preconditioned by the low-precision factors: the Krylov space of M⁻¹A is
+// built from M⁻¹r, where M⁻¹ = C·(L·U)⁻¹·P·R is the correction solve above
+// (scalings and interchanges included), orthogonalized by classical
+// Gram-Schmidt applied twice, and the small least-squares problem is updated
+// by Givens rotations (Carson and Higham's GMRES-based refinement). All
+// right-hand sides run together, each with its own basis and rotations; a
+// column stops once its preconditioned residual has dropped by kGmTol.
+constexpr int kGmMax = 40;        // Arnoldi steps per sweep (restart length)
+constexpr int kGmTotal = 200;     // Arnoldi steps per solve before giving up
+constexpr double kGmTol = 1e-6;   // relative reduction of the preconditioned residual
+constexpr int kGmProbe = 12;      // after this many steps of a sweep, its rate so far must reach
+                                  // kGmTol within the solve's remaining Arnoldi budget, else
+                                  // the solve is abandoned: M⁻¹A then has too many scattered
+                                  // eigenvalues for a short Krylov space (kappa·u_f well above 1)
+constexpr int kGmH = kGmMax + 1;  // rows of each column's Hessenberg matrix
+
+struct GmWork {
+    double *V = nullptr;      // kGmH blocks of n×nrhs: V_j(r, c) = V[(j·nrhs + c)·n + r]
+    double *H = nullptr;      // per column kGmH × kGmMax, column-major
+    double *hv = nullptr;     // per column kGmH: second projection pass, new norm
+    double *cs = nullptr, *sn = nullptr;   // per column kGmMax rotations
+    double *g = nullptr;      // per column kGmH: rotated right-hand side
+    double *y = nullptr;      // per column kGmMax: least-squares solution
+    double *beta = nullptr;   // per column: ||M⁻¹r||
+    double *flag = nullptr;   // [0]: largest residual ratio of unfinished columns
+    int *kk = nullptr;        // per column: Arnoldi steps that count
+    int *done = nullptr;      // per column: finished
+};
+
+// hout[c·ldh + i] = V_i(:, c)ᵀ·W(:, c), i < cnt (a workgroup per (i, c))
+__global__ __launch_bounds__(256) void gm_dot_k(long long n, long long nrhs, const double *__restrict__ V,
+                                                const double *__restrict__ W, double *hout, long long ldh) {
+    const long long i = blockIdx.x, c = blockIdx.y;
+    const double *v = V + (i * nrhs + c) * n, *w = W + c * n;
+    __shared__ double red[256];
+    double s = 0.0;
+    for (long long r = threadIdx.x; r < n; r += 256) s = fma(v[r], w[r], s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) hout[c * ldh + i] = red[0];
+}
+
+// W(:, c) -= Σ_{i<cnt} h[c·ldh + i]·V_i(:, c)
+__global__ void gm_orth_k(long long n, long long nrhs, const double *__restrict__ V, int cnt,
+                          const double *__restrict__ h, long long ldh, double *W) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long c = blockIdx.y;
+    if (r >= n) return;
+    double acc = 0.0;
+    for (int i = 0; i < cnt; ++i) acc = fma(h[c * ldh + i], V[((long long)i * nrhs + c) * n + r], acc);
+    W[c * n + r] -= acc;
+}
+
+// nrm[c·ld] = ||W(:, c)||, then W(:, c) /= nrm (left at zero when nrm is 0)
+__global__ __launch_bounds__(256) void gm_norm_scale_k(long long n, double *W, double *nrm, long long ld) {
+    const long long c = blockIdx.x;
+    double *w = W + c * n;
+    __shared__ double red[256];
+    double s = 0.0;
+    for (long long r = threadIdx.x; r < n; r += 256) s = fma(w[r], w[r], s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    const double nv = sqrt(red[0]);
+    if (threadIdx.x == 0) nrm[c * ld] = nv;
+    if (nv > 0.0) {
+        const double inv = 1.0 / nv;
+        for (long long r = threadIdx.x; r < n; r += 256) w[r] *= inv;
+    }
+}
+
+// start of a sweep: beta = ||M⁻¹r|| per column (from gm_norm_scale_k into hv[c·kGmH])
+__global__ void gm_init_k(long long nrhs, GmWork gw) {
+    for (long long c = threadIdx.x; c < nrhs; c += blockDim.x) {
+        const double b = gw.hv[c * kGmH];
+        gw.beta[c] = b;
+        gw.g[c * kGmH] = b;
+        gw.kk[c] = 0;
+        gw.done[c] = !(b > 0.0) || !isfinite(b);
+    }
+}
+
+// Arnoldi step j of every unfinished column: add the second projection pass,
+// apply the earlier rotations to the new Hessenberg column, form the rotation
+// that zeroes its subdiagonal, update g; flag[0] = the largest
+// |g_{j+1}| / beta of the columns still running (0 when all have finished).
+__global__ __launch_bounds__(256) void gm_givens_k(long long nrhs, int j, GmWork gw) {
+    __shared__ double red[256];
+    double mx = 0.0;
+    for (long long c = threadIdx.x; c < nrhs; c += 256) {
+        if (gw.done[c]) continue;
+        double *h = gw.H + c * kGmH * kGmMax + (long long)j * kGmH;
+        const double *h2 = gw.hv + c * kGmH;
+        for (int i = 0; i <= j; ++i) h[i] += h2[i];
+        h[j + 1] = h2[j + 1];
+        double *cs = gw.cs + c * kGmMax, *sn = gw.sn + c * kGmMax, *g = gw.g + c * kGmH;
+        for (int i = 0; i < j; ++i) {
+            const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+            h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+            h[i] = t;
+        }
+        const double a = h[j], b = h[j + 1];
+        const double r = hypot(a, b);
+        if (!(r > 0.0) || !isfinite(r)) {   // singular step: the least squares stop before it
+            gw.done[c] = 1;
+            continue;
+        }
+        cs[j] = a / r;
+        sn[j] = b / r;
+        h[j] = r;
+        h[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        gw.kk[c] = j + 1;
+        const double res = fabs(g[j + 1]) / gw.beta[c];
+        if (res <= kGmTol || !(h2[j + 1] > 0.0)) gw.done[c] = 1;
+        else if (res > mx || res != res) mx = res;
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k && (red[threadIdx.x + k] > red[threadIdx.x] || red[threadIdx.x + k] != red[threadIdx.x + k]))
+            red[threadIdx.x] = red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gw.flag[0] = red[0];
+}
+
+// y = R⁻¹·g over each column's kk steps (upper triangular back substitution)
+__global__ void gm_backsolve_k(long long nrhs, GmWork gw) {
+    for (long long c = threadIdx.x; c < nrhs; c += blockDim.x) {
+        const int k = gw.kk[c];
+        const double *H = gw.H + c * kGmH * kGmMax, *g = gw.g + c * kGmH;
+        double *y = gw.y + c * kGmMax;
+        for (int i = k - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int l = i + 1; l < k; ++l) s -= H[(long long)l * kGmH + i] * y[l];
+            y[i] = s / H[(long long)i * kGmH + i];
+        }
+    }
+}
+
+// X(:, c) += Σ_{l<kk} y_l·V_l(:, c)
+__global__ void gm_update_k(long long n, long long nrhs, GmWork gw, double *X, long long ldx) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long c = blockIdx.y;
+    if (r >= n) return;
+    const int k = gw.kk[c];
+    const double *y = gw.y + c * kGmMax;
+    double acc = 0.0;
+    for (int l = 0; l < k; ++l) acc = fma(y[l], gw.V[((long long)l * nrhs + c) * n + r], acc);
+    X[r + c * ldx] += acc;
+}
+
+static GmWork gmres_work(Ctx &c, long long n, long long nrhs) {
+    GmWork gw;
+    const size_t per = (size_t)nrhs * (size_t)(kGmH * kGmMax + 2 * kGmH + 3 * kGmMax + 1);
+    const size_t dbl = (size_t)kGmH * n * nrhs + per + 1;
+    const size_t bytes = dbl * sizeof(double) + 2 * (size_t)nrhs * sizeof(int);
+    char *p = (char *)workspace(c, SL_GM, bytes);
+    if (!p) return gw;
+    double *d = (double *)p;
+    gw.V = d; d += (size_t)kGmH * n * nrhs;
+    gw.H = d; d += (size_t)nrhs * kGmH * kGmMax;
+    gw.hv = d; d += (size_t)nrhs * kGmH;
+    gw.g = d; d += (size_t)nrhs * kGmH;
+    gw.cs = d; d += (size_t)nrhs * kGmMax;
+    gw.sn = d; d += (size_t)nrhs * kGmMax;
+    gw.y = d; d += (size_t)nrhs * kGmMax;
+    gw.beta = d; d += (size_t)nrhs;
+    gw.flag = d; d += 1;
+    gw.kk = (int *)d;
+    gw.done = gw.kk + nrhs;
+    return gw;
+}
+
+// W = A·X in FP64 (the residual kernel without b, or the GEMM for many columns)
+static void matvec(Ctx &c, long long n, long long nrhs, MixedWork &w, const double *X, long long ldx, double *W) {
+    if (nrhs <= kResidMaxRhs) {
+        trace_begin(c, PK_RESID);
+        const dim3 g((unsigned)((n + 63) / 64));
+        for (long long r0 = 0; r0 < nrhs; r0 += 2) {
+            if (nrhs - r0 >= 2)
+                hipLaunchKernelGGL((resid_k<2, true>), g, dim3(256), 0, c.stream, n, w.Af, w.ldaf, X + r0 * ldx, ldx,
+                                   (const double *)nullptr, 0LL, W + r0 * n, n);
+            else
+                hipLaunchKernelGGL((resid_k<1, true>), g, dim3(256), 0, c.stream, n, w.Af, w.ldaf, X + r0 * ldx, ldx,
+                                   (const double *)nullptr, 0LL, W + r0 * n, n);
+        }
+        RL_CHECK(hipGetLastError());
+        trace_end(c, PK_RESID, 2.0 * n * n * nrhs, 8.0 * n * n + 16.0 * n * nrhs);
+    } else {
+        gemm<double, double, double>(c, Mfma::F64, 'N', 'N', 0, n, nrhs, n, 1.0, w.Af, w.ldaf, X, ldx, 0.0, W, n);
+    }
+}
+
+// One GMRES-IR sweep: w.R holds r = b − A·x; X += d with d from GMRES on
+// M⁻¹A·d = M⁻¹r. Returns the Arnoldi steps taken (at most `budget`);
+// *hopeless is set (and X left alone) when, after kGmProbe steps, the
+// residual's average reduction per step would need more than `budget` steps
+// to reach kGmTol.
+static int gmres_sweep(Ctx &c, bool spd, char uplo, long long n, long long nrhs, MixedWork &w, GmWork &gw,
+                       double *X, long long ldx, int budget, bool *hopeless) {
+    *hopeless = false;
+    const dim3 g2(blocks(n), (unsigned)nrhs);
+    const double *cs = spd ? w.s1 : w.s2;
+    const long long blk = n * nrhs;
+    // V_0 = M⁻¹r / ||M⁻¹r||
+    correction(c, spd, uplo, n, nrhs, w);
+    hipLaunchKernelGGL(scale_rows_k, g2, dim3(256), 0, c.stream, n, nrhs, cs, (const double *)w.D, n, gw.V, n);
+    hipLaunchKernelGGL(gm_norm_scale_k, dim3((unsigned)nrhs), dim3(256), 0, c.stream, n, gw.V, gw.hv, (long long)kGmH);
+    hipLaunchKernelGGL(gm_init_k, dim3(1), dim3(256), 0, c.stream, nrhs, gw);
+    RL_CHECK(hipGetLastError());
+    int steps = 0;
+    for (int j = 0; j < kGmMax && steps < budget; ++j) {
+        double *Vj = gw.V + (long long)j * blk, *Vn = gw.V + (long long)(j + 1) * blk;
+        matvec(c, n, nrhs, w, Vj, n, w.R);
+        correction(c, spd, uplo, n, nrhs, w);
+        hipLaunchKernelGGL(scale_rows_k, g2, dim3(256), 0, c.stream, n, nrhs, cs, (const double *)w.D, n, Vn, n);
+        // classical Gram-Schmidt, twice
+        double *Hj = gw.H + (long long)j * kGmH;   // column j of column 0's matrix; stride kGmH·kGmMax per column
+        hipLaunchKernelGGL(gm_dot_k, dim3((unsigned)(j + 1), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs,
+                           (const double *)gw.V, (const double *)Vn, Hj, (long long)kGmH * kGmMax);
+        hipLaunchKernelGGL(gm_orth_k, g2, dim3(256), 0, c.stream, n, nrhs, (const double *)gw.V, j + 1,
+                           (const double *)Hj, (long long)kGmH * kGmMax, Vn);
+        hipLaunchKernelGGL(gm_dot_k, dim3((unsigned)(j + 1), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs,
+                           (const double *)gw.V, (const double *)Vn, gw.hv, (long long)kGmH);
+        hipLaunchKernelGGL(gm_orth_k, g2, dim3(256), 0, c.stream, n, nrhs, (const double *)gw.V, j + 1,
+                           (const double *)gw.hv, (long long)kGmH, Vn);
+        hipLaunchKernelGGL(gm_norm_scale_k, dim3((unsigned)nrhs), dim3(256), 0, c.stream, n, Vn, gw.hv + (j + 1),
+                           (long long)kGmH);
+        hipLaunchKernelGGL(gm_givens_k, dim3(1), dim3(256), 0, c.stream, nrhs, j, gw);
+        RL_CHECK(hipGetLastError());
+        ++steps;
+        const double ratio = fetch_scalar(c, gw.flag);
+        if (ratio == 0.0) break;   // every column has finished
+        if (steps == kGmProbe) {
+            // steps needed at the rate so far: log(kGmTol) / (log(ratio) / steps)
+            const bool slow = !(ratio < 1.0) || std::log(kGmTol) * steps / std::log(ratio) > (double)budget;
+            if (slow) { *hopeless = true; return steps; }
+        }
+    }
+    hipLaunchKernelGGL(gm_backsolve_k, dim3(1), dim3(256), 0, c.stream, nrhs, gw);
+    hipLaunchKernelGGL(gm_update_k, g2, dim3(256), 0, c.stream, n, nrhs, gw, X, ldx);
+    RL_CHECK(hipGetLastError());
+    return steps;
+}
+
+thread_local MixedStats t_mixed_stats;
+MixedStats mixed_last_stats() { return t_mixed_stats; }
+
 // Returns info; *iter and *berr as documented in relapack.h.
 int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const double *A, long long lda,
                 int *ipiv_out, const double *B, long long ldb, double *X, long long ldx, int prec, int *iter,
                 double *berr) {
     const double tol = 1e-14;
     const int max_sweeps = 30;
+    MixedStats &st = t_mixed_stats;
+    st = MixedStats();
     MixedWork w;
     w.S = (float *)workspace(c, SL_LP, (size_t)n * n * sizeof(float));
     w.ldaf = spd ? n : lda;
@@ -594,19 +861,44 @@ int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const 
         const double *cs = spd ? w.s1 : w.s2;
         hipLaunchKernelGGL(scale_rows_k, dim3(blocks(n), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs, cs,
                            w.D, n, X, ldx);
+        // plain refinement while each sweep cuts eta at least fourfold; then
+        // GMRES-IR, until eta stops halving (twice) or the Arnoldi budget is spent
         double prev = INFINITY;
+        bool use_gmres = false;
+        int gm_left = kGmTotal, slow = 0;
+        GmWork gw;
         for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
             eta = residual_eta(c, n, nrhs, w, B, ldb, X, ldx);
             if (eta <= tol) { status = 1; break; }
-            if (!(eta == eta) || (sweeps > 3 && eta > 0.5 * prev)) { status = -31; break; }
+            if (!(eta == eta)) { status = -31; break; }
+            if (!use_gmres && sweeps >= 2 && eta > 0.25 * prev) {
+                gw = gmres_work(c, n, nrhs);
+                if (!gw.V) return -1000 - (int)hipErrorOutOfMemory;
+                use_gmres = true;
+                st.switched_at = sweeps;
+            } else if (use_gmres && eta > 0.5 * prev) {
+                if (++slow >= 2) { status = -31; break; }
+            }
+            if (use_gmres && gm_left <= 0) { status = -31; break; }
             prev = eta;
-            correction(c, spd, uplo, n, nrhs, w);
-            hipLaunchKernelGGL(axpy_rows_k, dim3(blocks(n), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs, cs,
-                               w.D, n, X, ldx);
+            if (use_gmres) {
+                bool hopeless = false;
+                const int k = gmres_sweep(c, spd, uplo, n, nrhs, w, gw, X, ldx, gm_left, &hopeless);
+                gm_left -= k;
+                st.gmres_steps += k;
+                st.gmres_sweeps++;
+                if (hopeless) { status = -31; break; }
+            } else {
+                correction(c, spd, uplo, n, nrhs, w);
+                hipLaunchKernelGGL(axpy_rows_k, dim3(blocks(n), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs, cs,
+                                   w.D, n, X, ldx);
+            }
         }
         if (status == 0) status = -31;
     }
 
+    st.sweeps = sweeps;
+    st.status = status;
     if (status == 1) {
         *iter = sweeps;
         *berr = eta;

@@ -92,30 +92,98 @@ def _solve(kind, a, b, prec, uplo="L"):
     return info, it, berr, to_host(X)
 
 
-@pytest.mark.parametrize("kind", ["spd", "general"])
-@pytest.mark.parametrize("prec", [32, "fp16", "bf16"])
-@pytest.mark.parametrize("kappa", [1e2, 1e6])
-def test_mixed_solve_reaches_1e14(orc, kind, prec, kappa):
-    n, nrhs = 600, 3
-    a, b, x0 = gen.conditioned(n, kappa, kind, nrhs=nrhs, seed=int(np.log10(kappa)))
-    info, it, berr, x = _solve(kind, a, b, prec)
-    assert info == 0
+# What the refinement delivers at n = 600, three right-hand sides, on the
+# conditioned systems (sigma geometric from 1 to 1/kappa): > 0 the sweeps of a
+# low-precision solve that converged; -3 the low-precision Cholesky failed
+# (the factors of the scaled matrix are no longer positive definite once
+# kappa times the operands' unit roundoff passes 1); -31 refinement and
+# GMRES-IR stalled (about half of M⁻¹A's eigenvalues are scattered outliers
+# when kappa·u_f >> 1, too many for a short Krylov space). Every case ends
+# with eta <= 1e-14, the fallbacks through the FP64 factorization.
+CONVERGES = [("spd", 32, 1e2), ("spd", "fp16", 1e2), ("spd", "bf16", 1e2), ("spd", 32, 1e6),
+             ("general", 32, 1e2), ("general", "fp16", 1e2), ("general", "bf16", 1e2), ("general", 32, 1e6)]
+FALLS_BACK = [("spd", "fp16", 1e6, -3), ("spd", "bf16", 1e6, -3), ("spd", 32, 1e10, -3),
+              ("spd", "fp16", 1e10, -3), ("spd", "bf16", 1e10, -3),
+              ("general", "fp16", 1e6, -31), ("general", "bf16", 1e6, -31), ("general", 32, 1e10, -31),
+              ("general", "fp16", 1e10, -31), ("general", "bf16", 1e10, -31)]
+
+
+def _check_solution(orc, a, b, x, x0, kappa, berr):
     eta, _ = orc.backward_error(a, x, b)
-    assert eta <= 1e-14, (it, berr, eta)
-    assert berr <= 1e-14 and it != 0
-    if prec == 32 and kappa == 1e2:
-        assert 0 < it <= 6   # FP32 factors at kappa 1e2 refine in a few sweeps
+    assert eta <= 1e-14, eta
+    assert berr <= 1e-14
+    assert abs(berr - eta) <= 0.5 * eta + 1e-17
     # forward error consistent with kappa·eta
     assert rel_fro(x, x0) <= max(1e-10, 50 * kappa * 1e-14)
 
 
+@pytest.mark.parametrize("kind,prec,kappa", CONVERGES)
+def test_mixed_converges_in_low_precision(orc, kind, prec, kappa):
+    n, nrhs = 600, 3
+    a, b, x0 = gen.conditioned(n, kappa, kind, nrhs=nrhs, seed=int(np.log10(kappa)))
+    info, it, berr, x = _solve(kind, a, b, prec)
+    assert info == 0
+    assert it > 0, (kind, prec, kappa, it)   # no FP64 fallback
+    if prec == 32 and kappa == 1e2:
+        assert it <= 6   # FP32 factors at kappa 1e2 refine in a few sweeps
+    assert rl.mixed_last()["sweeps"] == it
+    _check_solution(orc, a, b, x, x0, kappa, berr)
+
+
+@pytest.mark.parametrize("kind,prec,kappa,code", FALLS_BACK)
+def test_mixed_falls_back_with_its_code(orc, kind, prec, kappa, code):
+    n, nrhs = 600, 3
+    a, b, x0 = gen.conditioned(n, kappa, kind, nrhs=nrhs, seed=int(np.log10(kappa)))
+    info, it, berr, x = _solve(kind, a, b, prec)
+    assert info == 0
+    assert it == code, (kind, prec, kappa, it)
+    st = rl.mixed_last()
+    if code == -3:
+        assert st["sweeps"] == 0
+    else:
+        assert st["gmres_from"] > 0 and st["gmres_steps"] > 0   # GMRES-IR was tried first
+    _check_solution(orc, a, b, x, x0, kappa, berr)
+
+
+def test_gmres_ir_converges_where_plain_refinement_is_slow(orc):
+    """BF16 LU of a general n = 4096 system at kappa = 1e2: each plain sweep
+    cuts eta by less than 4, so the solve switches to GMRES-IR after the
+    second sweep and converges without the FP64 fallback."""
+    n = 4096
+    a, b, x0 = gen.conditioned(n, 1e2, "general", nrhs=3, seed=2)
+    info, it, berr, x = _solve("general", a, b, "bf16")
+    st = rl.mixed_last()
+    assert info == 0 and it > 0, (it, st)
+    assert st["gmres_from"] == 2 and st["gmres_sweeps"] >= 1 and 0 < st["gmres_steps"] <= 200
+    _check_solution(orc, a, b, x, x0, 1e2, berr)
+
+
+@pytest.mark.parametrize("kind", ["spd", "general"])
+@pytest.mark.parametrize("prec", [32, "fp16"])
+@pytest.mark.parametrize("nrhs", [16, 64])
+def test_mixed_many_right_hand_sides(orc, kind, prec, nrhs):
+    """Many right-hand sides (the blocked correction solves and the GEMM
+    residual): every column reaches 1e-14 in low precision."""
+    n = 700
+    a, b, x0 = gen.conditioned(n, 1e2, kind, nrhs=nrhs, seed=7)
+    info, it, berr, x = _solve(kind, a, b, prec)
+    assert info == 0 and it > 0, it
+    _check_solution(orc, a, b, x, x0, 1e2, berr)
+
+
 def test_mixed_upper_and_fallback(orc):
     n = 300
+    # upper triangle, converging in FP16
+    a, b, x0 = gen.conditioned(n, 1e2, "spd", nrhs=2, seed=4)
+    info, it, berr, x = _solve("spd", a, b, "fp16", uplo="U")
+    assert info == 0 and it > 0, it
+    _check_solution(orc, a, b, x, x0, 1e2, berr)
+    # upper triangle at kappa 1e12: the FP16 Cholesky fails, the FP64 one solves it
     a, b, x0 = gen.conditioned(n, 1e12, "spd", nrhs=2, seed=4)
     info, it, berr, x = _solve("spd", a, b, "fp16", uplo="U")
-    assert info == 0
+    assert info == 0 and it == -3, it
     eta, _ = orc.backward_error(a, x, b)
-    assert eta <= 1e-14 or it < 0
+    assert eta <= 1e-14 and berr <= 1e-14
     # not positive definite: the low-precision and the FP64 factorizations both fail
     bad = gen.spd_bbt(n, seed=1)
     bad[5, 5] = -100.0
