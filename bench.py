@@ -285,39 +285,31 @@ def variants(n: int, stream, reps: int = 3):
 
 def batched(count: int, stream, reps: int = 3, seed: int = 4):
     """The batched workload of uneven sizes: ``count`` SPD matrices with n
-    uniform in [8, 512] (A = B·Bᵀ + n·I, B ~ U[-1, 1]) and ``count`` general
-    matrices with n uniform in [8, 256] (U[-1, 1]), all sizes from one seed,
-    each routine one call over its whole batch, in FP64 and FP32 (the FP64
-    inputs rounded). Median of ``reps`` calls after an untimed one, the inputs
-    restored before each. The bound is the per-matrix roofline summed over the
-    batch: max(flops / matrix peak, bytes / HBM bandwidth) with n³/3 flops and
-    8n² B (Cholesky), 2n³/3 flops and 16n² B (LU), halved bytes in FP32."""
+    uniform in [8, 512] and ``count`` general matrices with n uniform in
+    [8, 256], sizes and per-matrix seeds from one master seed
+    (``gen.batch_sizes`` / ``gen.batch_seeds``), each matrix from the PCG64
+    recipes (SPD: the draws of ``gen.spd_bbt``, B·Bᵀ + n·I formed on the
+    device; general: ``gen.general_uniform``); each routine one call over its
+    whole batch, in FP64 and FP32 (the FP64 inputs rounded). Median of
+    ``reps`` calls after an untimed one (the first call captures the launch
+    graph), the inputs restored before each. The bound is the per-matrix
+    roofline summed over the batch: max(flops / matrix peak, bytes / HBM
+    bandwidth) with n³/3 flops and 8n² B (Cholesky), 2n³/3 flops and 16n² B
+    (LU), halved bytes in FP32."""
     import numpy as np
     import torch
 
+    import gen
     import paper_1602_06763_amd as rl
+    from paper_1602_06763_amd.autotune import batch_buffer
 
-    g = np.random.default_rng(seed)
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    out = {"count_spd": count, "count_general": count, "n_spd": "U{8..512}", "n_general": "U{8..256}"}
+    out = {"count_spd": count, "count_general": count, "n_spd": "U{8..512}", "n_general": "U{8..256}",
+           "inputs": "PCG64 per matrix (gen.batch_sizes / batch_seeds, master seeds %d and %d)" % (seed, seed + 2)}
 
     def build(ns, spd):
-        offs = np.concatenate([[0], np.cumsum(ns.astype(np.int64) ** 2)])
-        buf = torch.empty(int(offs[-1]), dtype=torch.float64, device="cuda")
-        gen_t = torch.Generator(device="cuda")
-        gen_t.manual_seed(seed + (1 if spd else 2))
-        if spd:
-            for n in np.unique(ns):
-                idx = np.nonzero(ns == n)[0]
-                B = torch.rand((len(idx), int(n), int(n)), dtype=torch.float64, device="cuda", generator=gen_t) * 2 - 1
-                A = torch.bmm(B, B.transpose(1, 2).contiguous())
-                A.diagonal(dim1=1, dim2=2).add_(float(n))
-                for q, i in enumerate(idx):
-                    buf[int(offs[i]):int(offs[i + 1])].copy_(A[q].reshape(-1))
-                del B, A
-        else:
-            buf.uniform_(-1.0, 1.0, generator=gen_t)
-        return buf, offs
+        seeds = gen.batch_seeds(len(ns), seed if spd else seed + 2)
+        return batch_buffer(ns, seeds, spd, torch.float64)
 
     def run(name, ns, buf, offs, call, flops, nbytes, peak, ipiv=None):
         esz = buf.element_size()
@@ -347,8 +339,8 @@ def batched(count: int, stream, reps: int = 3, seed: int = 4):
         del src
         return ms
 
-    ns_spd = g.integers(8, 513, size=count)
-    ns_ge = g.integers(8, 257, size=count)
+    ns_spd = gen.batch_sizes(count, 8, 512, seed)
+    ns_ge = gen.batch_sizes(count, 8, 256, seed + 2)
     chol_f, lu_f = (lambda n: n ** 3 / 3.0), (lambda n: 2.0 * n ** 3 / 3.0)
     buf, offs = build(ns_spd, True)
     run("dpotrf", ns_spd, buf, offs, lambda nv, p, info: rl.potrf_batched("L", count, nv, p, nv, info),

@@ -27,6 +27,10 @@ these stand in for them):
 * ``triangular``    a row-diagonally-dominant triangle (triangular inverse and
                     product inputs); ``unit_bidiagonal`` a triangle with a
                     closed-form inverse.
+* ``batch_sizes`` / ``batch_seeds``  the uneven batched workload: sizes
+                    uniform in [lo, hi] and one seed per matrix, both from one
+                    master seed; matrix i is then ``spd_bbt(n_i, seed_i)`` or
+                    ``general_uniform(n_i, n_i, seed_i)``.
 """
 from __future__ import annotations
 
@@ -50,12 +54,16 @@ def spd_bbt(n: int, seed: int = 0) -> np.ndarray:
     The product is mirrored from its lower triangle so that A is exactly
     symmetric. κ₂(A) ≈ 7/3 for large n (Marchenko–Pastur edge 4n/3 over n).
     """
-    g = rng(seed)
-    b = g.uniform(-1.0, 1.0, size=(n, n))
+    b = spd_bbt_draws(n, seed)
     a = b @ b.T
     a = np.tril(a) + np.tril(a, -1).T
     a[np.diag_indices(n)] += float(n)
     return _fortran(a)
+
+
+def spd_bbt_draws(n: int, seed: int = 0) -> np.ndarray:
+    """The B of ``spd_bbt(n, seed)``: one ``uniform(-1, 1, size=(n, n))`` call."""
+    return rng(seed).uniform(-1.0, 1.0, size=(n, n))
 
 
 def general_uniform(m: int, n: int | None = None, seed: int = 0) -> np.ndarray:
@@ -302,3 +310,15 @@ def conditioned_torch(n: int, kappa: float, kind: str = "spd", nrhs: int = 1, se
     b = a @ x0
     colmajor = lambda t: t.T.contiguous().T
     return colmajor(a), colmajor(b), colmajor(x0)
+
+
+def batch_sizes(count: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    """Sizes of a batch: ``count`` integers uniform in [lo, hi] (one
+    ``integers`` call of the master generator)."""
+    return rng(seed).integers(lo, hi + 1, size=count).astype(np.int64)
+
+
+def batch_seeds(count: int, seed: int) -> np.ndarray:
+    """Per-matrix seeds of a batch: ``count`` 62-bit integers from the
+    generator of ``seed + 1`` (the sizes use ``seed`` itself)."""
+    return rng(seed + 1).integers(0, 2**62, size=count, dtype=np.int64)

@@ -295,9 +295,14 @@ void relapack_sgetrf(int m, int n, float *A, int lda, int *ipiv, int *info);
  *   info[b] (device): 0, k > 0 (leading minor k not positive definite; that
  *   matrix's factorization stopped there), -2 (n[b] < 0 or n[b] > 512),
  *   -4 (lda[b] < max(1, n[b])).
- *   Batches larger than the chip holds at once (two workgroups per CU) run
- *   in order of size, largest first; the order (count ints) is computed on
- *   the device into the library's workspace.
+ *   One persistent launch: as many workgroups as the chip holds at once take
+ *   the matrices from a device work queue in order of size, largest first
+ *   (the order, count ints, and the queue counter live in the library's
+ *   workspace). Each matrix's recursion uses the leaf size and product tile
+ *   edge of its size bucket (relapack_batched_tune). The launch sequence is
+ *   captured into a HIP graph the first time a (routine, count, arrays,
+ *   tuning) combination is seen and replayed afterwards (at most 16 graphs
+ *   are kept; relapack_batched_graphs(0) launches directly instead).
  * Returns 0, -1 (uplo), -2 (count < 0), -3 (a null array with count > 0),
  * or -1000 - hipError_t. Stream-ordered; returns after completion.
  */
@@ -312,8 +317,8 @@ int relapack_spotrf_batched(char uplo, int count, const int *n, float *const *A,
  *   to the caller's device array of n[b] ints (1-based pivot rows).
  *   info[b] (device): 0, k > 0 (U(k,k) exactly zero, the first such k; the
  *   factorization completes), -2 (n[b] < 0 or n[b] > 256), -4 (lda[b] <
- *   max(1, n[b])). Large batches run in order of size as in
- *   relapack_dpotrf_batched.
+ *   max(1, n[b])). Persistent launch, work queue in order of size, tuning
+ *   and graph capture as in relapack_dpotrf_batched.
  * Returns 0, -1 (count < 0), -2 (a null array with count > 0), or
  * -1000 - hipError_t. Stream-ordered; returns after completion.
  */
@@ -321,6 +326,23 @@ int relapack_dgetrf_batched(int count, const int *n, double *const *A, const int
                             int *info);
 int relapack_sgetrf_batched(int count, const int *n, float *const *A, const int *lda, int *const *ipiv,
                             int *info);
+
+/*
+ * Per-size-bucket choices of the batched routines (routine: 0 dpotrf,
+ * 1 spotrf, 2 dgetrf, 3 sgetrf; bucket: 0 n <= 64, 1 n <= 128, 2 n <= 256,
+ * 3 above): leaf = the crossover of each matrix's recursion (Cholesky 32 or
+ * 64, LU panel width 16 or 32), tile = the edge of the matrix-core product
+ * tiles (32 or 64). The defaults are the table measured by
+ * paper_1602_06763_amd/autotune.py on MI355X. Returns 0, -1 (routine),
+ * -2 (bucket), -3 (a value not offered). Not thread-safe against running
+ * batched calls of other threads (their next call picks the new values up).
+ */
+int relapack_batched_tune(int routine, int bucket, int leaf, int tile);
+int relapack_batched_tune_get(int routine, int bucket, int *leaf, int *tile);
+
+/* Batched calls through captured HIP graphs (on = 1, the default) or by
+ * direct launches (on = 0). Tracing always launches directly. */
+void relapack_batched_graphs(int on);
 
 /* ---- measurement and inspection ------------------------------------------ */
 

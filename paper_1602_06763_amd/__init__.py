@@ -67,6 +67,9 @@ _SIGS = {
     "relapack_spotrf_batched": ([_c_char, _c_int, _vp, _vp, _vp, _vp], _c_int),
     "relapack_dgetrf_batched": ([_c_int, _vp, _vp, _vp, _vp, _vp], _c_int),
     "relapack_sgetrf_batched": ([_c_int, _vp, _vp, _vp, _vp, _vp], _c_int),
+    "relapack_batched_tune": ([_c_int, _c_int, _c_int, _c_int], _c_int),
+    "relapack_batched_tune_get": ([_c_int, _c_int, _ip, _ip], _c_int),
+    "relapack_batched_graphs": ([_c_int], None),
     "relapack_trace_enable": ([_c_int], None),
     "relapack_trace_collect": ([_dp, _c_int], _c_int),
     "relapack_plan": ([ctypes.c_char_p, _c_ll, _c_ll, _c_int, _llp, _c_ll], _c_ll),
@@ -396,6 +399,28 @@ def potrf_batched(uplo: str, count: int, n, A_ptrs, lda, info, single: bool = Fa
         _check_vec(t, dt, count, what)
     f = lib().relapack_spotrf_batched if single else lib().relapack_dpotrf_batched
     return f(_b(uplo), count, _ptr(n), _ptr(A_ptrs), _ptr(lda), _ptr(info))
+
+
+BATCH_ROUTINES = {"dpotrf": 0, "spotrf": 1, "dgetrf": 2, "sgetrf": 3}
+
+
+def batched_tune(routine, bucket: int, leaf: int, tile: int) -> int:
+    """relapack_batched_tune: set one size bucket's leaf size and tile edge."""
+    return lib().relapack_batched_tune(BATCH_ROUTINES.get(routine, routine), bucket, leaf, tile)
+
+
+def batched_tune_get(routine, bucket: int):
+    """(leaf, tile) of one size bucket."""
+    leaf, tile = ctypes.c_int(0), ctypes.c_int(0)
+    r = lib().relapack_batched_tune_get(BATCH_ROUTINES.get(routine, routine), bucket, ctypes.byref(leaf),
+                                        ctypes.byref(tile))
+    if r != 0:
+        raise ValueError(f"routine {routine!r} / bucket {bucket}: {r}")
+    return leaf.value, tile.value
+
+
+def batched_graphs(on: bool) -> None:
+    lib().relapack_batched_graphs(1 if on else 0)
 
 
 def getrf_batched(count: int, n, A_ptrs, lda, ipiv_ptrs, info, single: bool = False) -> int:

@@ -418,6 +418,20 @@ extern "C" {
 
 int relapack_version(void) { return 1; }
 
+int relapack_batched_tune(int routine, int bucket, int leaf, int tile) {
+    if (routine < 0 || routine > 3) return -1;
+    if (bucket < 0 || bucket > 3) return -2;
+    return batched_tune_set(routine, bucket, leaf, tile) ? 0 : -3;
+}
+
+int relapack_batched_tune_get(int routine, int bucket, int *leaf, int *tile) {
+    if (routine < 0 || routine > 3) return -1;
+    if (bucket < 0 || bucket > 3) return -2;
+    return batched_tune_get(routine, bucket, leaf, tile) ? 0 : -2;
+}
+
+void relapack_batched_graphs(int on) { batched_graphs(on != 0); }
+
 int relapack_set_stream(void *stream) {
     ctx().stream = (hipStream_t)stream;
     return 0;
@@ -426,6 +440,7 @@ int relapack_set_stream(void *stream) {
 void *relapack_get_stream(void) { return (void *)ctx().stream; }
 
 void relapack_finalize(void) {
+    batched_release();
     for (int i = 0; i < kMaxDev; ++i) {
         // the same lock order as a call: the device's call lock, then the state lock
         std::lock_guard<std::recursive_mutex> call_lk(g_call_mu[i]);

@@ -1,6 +1,11 @@
 // Batched factorizations: many independent small matrices of uneven sizes in
-// one launch, one workgroup per matrix, each matrix's recursion run on the
-// device by that workgroup.
+// one persistent launch, each matrix's recursion run on the device by one
+// workgroup. The workgroups (as many as the chip holds at once) take matrices
+// from a device work queue in order of size, largest first; the leaf size and
+// the matrix-core tile edge are chosen per size bucket from a table measured
+// on the device (batched_tune.hpp); the launch sequence of a call (queue
+// reset, size order, persistent kernel) is captured once into a HIP graph and
+// replayed for later calls with the same arguments.
 //
 // The recursion is the one of the single-matrix routines (Sec. 3: split at
 // n/2 rounded to the 64-wide matrix-core tile, leaves below the crossover;
@@ -25,6 +30,9 @@
 // operation is inlined once and the kernel makes no calls.
 #include "common.hpp"
 #include "wg.hpp"
+#include "batched_tune.hpp"
+
+#include <mutex>
 
 namespace rl {
 
@@ -76,57 +84,63 @@ __device__ __forceinline__ BatchLds<T> &blds() {
 }
 
 // C -= A·B by one workgroup on the matrix cores: C is M×N, A is M×K, B is
-// K×N. The workgroup takes 64×64 tiles of C in turn (each wave a 32×32
-// quarter, four 16×16 accumulators); K goes in chunks of 32 staged in LDS,
-// double buffered, the next chunk's loads in flight while the current one is
-// multiplied. Threads run along whichever index of an operand has unit
-// stride, so the loads are contiguous for every view the recursion passes.
-// TRI computes and writes only the lower triangle of C. Operands are read
-// with clamped indices (always inside the views) and zeroed outside them.
+// K×N. The workgroup takes tile×tile tiles of C in turn (tile 64 or 32, a
+// run-time choice so that one body serves both; each wave a quarter, 16×16
+// accumulators); K goes in chunks of 32 staged in LDS, double buffered, the
+// next chunk's loads in flight while the current one is multiplied. Threads
+// run along whichever index of an operand has unit stride, so the loads are
+// contiguous for every view the recursion passes. TRI computes and writes
+// only the lower triangle of C. Operands are read with clamped indices
+// (always inside the views) and zeroed outside them.
 template <typename T, bool TRI>
-__device__ __forceinline__ void wg_gemm(int M, int N, int K, WgMat<const T> A, WgMat<const T> B,
-                                                  WgMat<T> C) {
+__device__ __forceinline__ void wg_gemm_t(int tile, int M, int N, int K, WgMat<const T> A, WgMat<const T> B,
+                                          WgMat<T> C) {
     typedef LeafMfma<T> Op;
     typedef typename Op::acc_t acc_t;
     if (M <= 0 || N <= 0 || K <= 0) return;
     GemmLdsB<T> &L = blds<T>().gm;
+    const int TL = tile == 32 ? 32 : 64, sh = tile == 32 ? 5 : 6;   // tile edge and its log2
+    const int WT = TL >> 1, sub = WT >> 4, ld = TL >> 3;             // wave tile, 16-blocks per edge, loads
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int wi = 32 * (wave & 1), wj = 32 * (wave >> 1);   // this wave's quarter of the tile
+    const int wi = WT * (wave & 1), wj = WT * (wave >> 1);   // this wave's quarter of the tile
     const bool a_rows = A.r == 1, b_cols = B.c == 1;
-    const int tm = (M + 63) / 64, tn = (N + 63) / 64;
-    for (int tile = 0; tile < tm * tn; ++tile) {
-        const int bi = tile % tm, bj = tile / tm;
+    const int tm = (M + TL - 1) >> sh, tn = (N + TL - 1) >> sh;
+    for (int t = 0; t < tm * tn; ++t) {
+        const int bi = t % tm, bj = t / tm;
         if (TRI && bi < bj) continue;   // uniform across the workgroup
-        const int i0 = 64 * bi, j0 = 64 * bj;
+        const int i0 = TL * bi, j0 = TL * bj;
         T ra[8], rb[8];
         auto fetch = [&](int k0) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int idx = tid + 256 * u;
-                const int ia = a_rows ? (idx & 63) : (idx >> 5), ka = a_rows ? (idx >> 6) : (idx & 31);
-                const int jb = b_cols ? (idx & 63) : (idx >> 5), kb = b_cols ? (idx >> 6) : (idx & 31);
+                const int ia = a_rows ? (idx & (TL - 1)) : (idx >> 5), ka = a_rows ? (idx >> sh) : (idx & 31);
+                const int jb = b_cols ? (idx & (TL - 1)) : (idx >> 5), kb = b_cols ? (idx >> sh) : (idx & 31);
                 const int gi = i0 + ia, gka = k0 + ka, gj = j0 + jb, gkb = k0 + kb;
+                const bool on = u < ld;
                 const T av = A(min(gi, M - 1), min(gka, K - 1)), bv = B(min(gkb, K - 1), min(gj, N - 1));
-                ra[u] = (gi < M && gka < K) ? av : T(0);
-                rb[u] = (gj < N && gkb < K) ? bv : T(0);
+                ra[u] = (on && gi < M && gka < K) ? av : T(0);
+                rb[u] = (on && gj < N && gkb < K) ? bv : T(0);
             }
         };
         auto stage = [&](int buf) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int idx = tid + 256 * u;
-                const int ia = a_rows ? (idx & 63) : (idx >> 5), ka = a_rows ? (idx >> 6) : (idx & 31);
-                const int jb = b_cols ? (idx & 63) : (idx >> 5), kb = b_cols ? (idx >> 6) : (idx & 31);
-                L.As[buf][ka][ia] = ra[u];
-                L.Bs[buf][kb][jb] = rb[u];
+                if (u < ld) {
+                    const int idx = tid + 256 * u;
+                    const int ia = a_rows ? (idx & (TL - 1)) : (idx >> 5), ka = a_rows ? (idx >> sh) : (idx & 31);
+                    const int jb = b_cols ? (idx & (TL - 1)) : (idx >> 5), kb = b_cols ? (idx >> sh) : (idx & 31);
+                    L.As[buf][ka][ia] = ra[u];
+                    L.Bs[buf][kb][jb] = rb[u];
+                }
             }
         };
         acc_t acc[2][2];
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int t = 0; t < 2; ++t) acc[s][t] = acc_t{0, 0, 0, 0};
+            for (int q = 0; q < 2; ++q) acc[s][q] = acc_t{0, 0, 0, 0};
         fetch(0);
         int buf = 0;
         for (int k0 = 0; k0 < K; k0 += 32) {
@@ -136,16 +150,20 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, WgMat<const T> A, W
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk) {
                 const int k = 4 * kk + lk;
-                T a[2], b[2];
+                if (sub == 2) {
+                    T a[2], b[2];
 #pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    a[s] = L.As[buf][k][wi + 16 * s + lr];
-                    b[s] = L.Bs[buf][k][wj + 16 * s + lr];
+                    for (int s = 0; s < 2; ++s) {
+                        a[s] = L.As[buf][k][wi + 16 * s + lr];
+                        b[s] = L.Bs[buf][k][wj + 16 * s + lr];
+                    }
+#pragma unroll
+                    for (int s = 0; s < 2; ++s)
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) acc[s][q] = Op::mma(a[s], b[q], acc[s][q]);
+                } else {
+                    acc[0][0] = Op::mma(L.As[buf][k][wi + lr], L.Bs[buf][k][wj + lr], acc[0][0]);
                 }
-#pragma unroll
-                for (int s = 0; s < 2; ++s)
-#pragma unroll
-                    for (int t = 0; t < 2; ++t) acc[s][t] = Op::mma(a[s], b[t], acc[s][t]);
             }
             buf ^= 1;
         }
@@ -153,11 +171,11 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, WgMat<const T> A, W
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
+            for (int q = 0; q < 2; ++q)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int i = i0 + wi + 16 * s + Op::row(lane, v), j = j0 + wj + 16 * t + lr;
-                    if (i < M && j < N && (!TRI || i >= j)) C(i, j) -= acc[s][t][v];
+                    const int i = i0 + wi + 16 * s + Op::row(lane, v), j = j0 + wj + 16 * q + lr;
+                    if (s < sub && q < sub && i < M && j < N && (!TRI || i >= j)) C(i, j) -= acc[s][q][v];
                 }
     }
 }
@@ -169,7 +187,7 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, WgMat<const T> A, W
 // beyond the triangle) and solved for 64 vectors at a time (16 per wave),
 // then the rows below it are updated on the matrix cores.
 template <typename T>
-__device__ __forceinline__ void wg_trsm(int t, int nvec, int unit, WgMat<const T> N, WgMat<T> X) {
+__device__ __forceinline__ void wg_trsm(int t, int nvec, int unit, WgMat<const T> N, WgMat<T> X, int tile) {
     if (t <= 0 || nvec <= 0) return;
     TrsmLds<T> &L = blds<T>().ts;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -200,7 +218,7 @@ __device__ __forceinline__ void wg_trsm(int t, int nvec, int unit, WgMat<const T
         }
         __syncthreads();
         if (J0 + tb < t)
-            wg_gemm<T, false>(t - J0 - tb, nvec, tb,
+            wg_gemm_t<T, false>(tile, t - J0 - tb, nvec, tb,
                               WgMat<const T>{N.p + (J0 + tb) * N.r + J0 * N.c, N.r, N.c},
                               WgMat<const T>{X.p + J0 * X.r, X.r, X.c},
                               WgMat<T>{X.p + (J0 + tb) * X.r, X.r, X.c});
@@ -222,7 +240,7 @@ constexpr int kBatchStack = 3 * 8 + 1;   // three frames per level, 8 levels cov
 // L22·L22ᵀ. Returns 0 or the first failing column (1-based, as potf2_block);
 // nothing after a failing leaf runs.
 template <typename T>
-__device__ __forceinline__ int potrf_b(int n, T *A, long long si, long long sj, BFrame *stk) {
+__device__ __forceinline__ int potrf_b(int n, T *A, long long si, long long sj, BFrame *stk, int leaf, int tile) {
     int sp = 0;
     if (threadIdx.x == 0) stk[0] = BFrame{0, 0, n, 0};
     sp = 1;
@@ -231,7 +249,7 @@ __device__ __forceinline__ int potrf_b(int n, T *A, long long si, long long sj, 
         const BFrame f = stk[--sp];
         __syncthreads();   // every thread has read the frame before it is overwritten
         T *Ao = A + f.off * si + f.off * sj;
-        if (f.kind == 0 && f.n <= kCholLeaf) {
+        if (f.kind == 0 && f.n <= leaf) {
             const int r = potf2_block(f.n, Ao, si, sj, blds<T>().p2);
             __syncthreads();
             if (r) return f.off + r;
@@ -247,8 +265,8 @@ __device__ __forceinline__ int potrf_b(int n, T *A, long long si, long long sj, 
         } else {
             const int n1 = f.n1, n2 = f.n - f.n1;
             // the rows of A21 are the vectors of the solve with the triangle L11
-            wg_trsm<T>(n1, n2, 0, WgMat<const T>{Ao, si, sj}, WgMat<T>{Ao + n1 * si, sj, si});
-            wg_gemm<T, true>(n2, n2, n1, WgMat<const T>{Ao + n1 * si, si, sj},
+            wg_trsm<T>(n1, n2, 0, WgMat<const T>{Ao, si, sj}, WgMat<T>{Ao + n1 * si, sj, si}, tile);
+            wg_gemm_t<T, true>(tile, n2, n2, n1, WgMat<const T>{Ao + n1 * si, si, sj},
                              WgMat<const T>{Ao + n1 * si, sj, si}, WgMat<T>{Ao + n1 * si + n1 * sj, si, sj});
             __syncthreads();
         }
@@ -388,7 +406,7 @@ __device__ __forceinline__ int wg_getf2(int n, T *A, long long lda, int c0, int 
 // zero pivot column (global, 1-based) or 0; the factorization always
 // completes.
 template <typename T>
-__device__ __forceinline__ int getrf_b(int n, T *A, long long lda, int *ipiv, BFrame *stk) {
+__device__ __forceinline__ int getrf_b(int n, T *A, long long lda, int *ipiv, BFrame *stk, int leaf, int tile) {
     int sp = 0, info = 0;
     if (threadIdx.x == 0) stk[0] = BFrame{0, 0, n, 0};
     sp = 1;
@@ -397,7 +415,7 @@ __device__ __forceinline__ int getrf_b(int n, T *A, long long lda, int *ipiv, BF
         const BFrame f = stk[--sp];
         __syncthreads();
         const int c0 = f.off;
-        if (f.kind == 0 && f.n <= kLuLeaf) {
+        if (f.kind == 0 && f.n <= leaf) {
             const int r = wg_getf2<T>(n, A, lda, c0, f.n, ipiv);
             if (info == 0) info = r;
         } else if (f.kind == 0) {
@@ -412,8 +430,8 @@ __device__ __forceinline__ int getrf_b(int n, T *A, long long lda, int *ipiv, BF
         } else {
             const int w1 = f.n1, w2 = f.n - f.n1;
             wg_trsm<T>(w1, w2, 1, WgMat<const T>{A + c0 + c0 * lda, 1, lda},
-                       WgMat<T>{A + c0 + (c0 + w1) * lda, 1, lda});
-            wg_gemm<T, false>(n - c0 - w1, w2, w1, WgMat<const T>{A + (c0 + w1) + c0 * lda, 1, lda},
+                       WgMat<T>{A + c0 + (c0 + w1) * lda, 1, lda}, tile);
+            wg_gemm_t<T, false>(tile, n - c0 - w1, w2, w1, WgMat<const T>{A + (c0 + w1) + c0 * lda, 1, lda},
                               WgMat<const T>{A + c0 + (c0 + w1) * lda, 1, lda},
                               WgMat<T>{A + (c0 + w1) + (c0 + w1) * lda, 1, lda});
             __syncthreads();
@@ -422,13 +440,12 @@ __device__ __forceinline__ int getrf_b(int n, T *A, long long lda, int *ipiv, BF
     return info;
 }
 
-// Launch order of a batch: matrix indices sorted by size, largest first (one
+// Order of the work queue: matrix indices sorted by size, largest first (one
 // counting sort in one workgroup; sizes outside [0, KMAX] go last, where the
-// factorization kernels reject them). Workgroups of similar sizes then run
-// side by side: over 20000 matrices of uniform random sizes the batched
-// Cholesky took 25.5 ms in size order against 29.8 ms in the given order, LU
-// 18.4 against 21.4 ms. The order within one size is arbitrary; every matrix
-// is factored by one workgroup either way, so results do not depend on it.
+// factorization kernels reject them), so the longest factorizations start
+// first and the short ones fill the tail. The order within one size is
+// arbitrary; every matrix is factored by one workgroup either way, so results
+// do not depend on it.
 template <int KMAX>
 __global__ __launch_bounds__(1024) void batch_order_k(int count, const int *__restrict__ nv,
                                                       int *__restrict__ perm) {
@@ -454,78 +471,240 @@ __global__ __launch_bounds__(1024) void batch_order_k(int count, const int *__re
     for (int i = tid; i < count; i += 1024) perm[atomicAdd(&start[key(i)], 1)] = i;
 }
 
+// Queue reset of a call (a kernel, so that the call's graph holds no memset).
+__global__ void batch_queue_reset_k(unsigned *q) {
+    if (threadIdx.x == 0) *q = 0u;
+}
+
+// Persistent batched Cholesky: each workgroup takes the next matrix of the
+// size order from the queue until the queue is exhausted (every workgroup
+// reaches that exit). Per matrix, the leaf size and tile edge of its size
+// bucket.
 template <typename T>
 __global__ __launch_bounds__(256, 2) void potrf_batched_k(int count, int upper, const int *__restrict__ nv,
                                                       T *const *__restrict__ Av, const int *__restrict__ ldav,
-                                                      int *__restrict__ infov, const int *__restrict__ perm) {
-    if ((int)blockIdx.x >= count) return;
-    const int b = perm ? perm[blockIdx.x] : (int)blockIdx.x;
+                                                      int *__restrict__ infov, const int *__restrict__ perm,
+                                                      unsigned *queue, BatchTune tune) {
     __shared__ BFrame stk[kBatchStack];
-    const int n = nv[b], lda = ldav[b];
-    int info = 0;
-    if (n < 0 || n > kBatchMaxSpd) info = -2;
-    else if (lda < max(1, n)) info = -4;
-    else if (n > 0) {
-        const long long si = upper ? lda : 1, sj = upper ? 1 : lda;
-        info = potrf_b<T>(n, Av[b], si, sj, stk);
+    __shared__ int item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();   // read by every thread before the next matrix's fetch overwrites it
+        if (item >= count) return;
+        const int b = perm[item];
+        const int n = nv[b], lda = ldav[b];
+        int info = 0;
+        if (n < 0 || n > kBatchMaxSpd) info = -2;
+        else if (lda < max(1, n)) info = -4;
+        else if (n > 0) {
+            const long long si = upper ? lda : 1, sj = upper ? 1 : lda;
+            const int bk = batch_bucket(n);
+            info = potrf_b<T>(n, Av[b], si, sj, stk, tune.leaf[bk], tune.tile[bk]);
+        }
+        if (threadIdx.x == 0) infov[b] = info;
+        __syncthreads();   // LDS of this matrix is free before the next one starts
     }
-    if (threadIdx.x == 0) infov[b] = info;
 }
 
 template <typename T>
 __global__ __launch_bounds__(256, 2) void getrf_batched_k(int count, const int *__restrict__ nv,
                                                       T *const *__restrict__ Av, const int *__restrict__ ldav,
                                                       int *const *__restrict__ ipivv, int *__restrict__ infov,
-                                                      const int *__restrict__ perm) {
-    if ((int)blockIdx.x >= count) return;
-    const int b = perm ? perm[blockIdx.x] : (int)blockIdx.x;
+                                                      const int *__restrict__ perm, unsigned *queue,
+                                                      BatchTune tune) {
     __shared__ BFrame stk[kBatchStack];
-    const int n = nv[b], lda = ldav[b];
-    int info = 0;
-    if (n < 0 || n > kBatchMaxGe) info = -2;
-    else if (lda < max(1, n)) info = -4;
-    else if (n > 0) info = getrf_b<T>(n, Av[b], lda, ipivv[b], stk);
-    if (threadIdx.x == 0) infov[b] = info;
+    __shared__ int item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= count) return;
+        const int b = perm[item];
+        const int n = nv[b], lda = ldav[b];
+        int info = 0;
+        if (n < 0 || n > kBatchMaxGe) info = -2;
+        else if (lda < max(1, n)) info = -4;
+        else if (n > 0) {
+            const int bk = batch_bucket(n);
+            info = getrf_b<T>(n, Av[b], lda, ipivv[b], stk, tune.leaf[bk], tune.tile[bk]);
+        }
+        if (threadIdx.x == 0) infov[b] = info;
+        __syncthreads();
+    }
 }
 
-// The size order for a batch of more matrices than fit on the chip at once
-// (two workgroups per CU), in the per-device workspace; *perm stays null for
-// smaller batches (given order). False if the workspace could not be had.
-template <int KMAX>
-static bool batch_order(Ctx &c, int count, const int *n, const int **perm) {
-    *perm = nullptr;
-    if (count <= 2 * c.num_cu) return true;
-    int *p = (int *)workspace(c, kSlotBatchOrder, (size_t)count * sizeof(int));
-    if (!p) return false;
-    rl_launch(c, batch_order_k<KMAX>, dim3(1), dim3(1024), 0, count, n, p);
-    RL_CHECK(hipGetLastError());
-    *perm = p;
+// ---- host side: tuning table, launch sequence, graph cache -------------------
+
+namespace {
+
+// routines: 0 dpotrf, 1 spotrf, 2 dgetrf, 3 sgetrf
+BatchTune g_tune[4] = {kTuneDefault[0], kTuneDefault[1], kTuneDefault[2], kTuneDefault[3]};
+bool g_graphs_on = true;
+
+struct BatchGraph {
+    bool used = false;
+    int device = -1, routine = -1, count = 0, upper = 0, grid = 0;
+    const void *n = nullptr, *A = nullptr, *lda = nullptr, *ipiv = nullptr, *info = nullptr;
+    const void *ws = nullptr;
+    BatchTune tune{};
+    hipGraphExec_t exec = nullptr;
+    unsigned long long stamp = 0;
+};
+constexpr int kGraphCache = 16;
+BatchGraph g_cache[kGraphCache];
+unsigned long long g_stamp = 0;
+hipStream_t g_cap[16] = {};
+std::mutex g_bmu;
+
+bool same_tune(const BatchTune &a, const BatchTune &b) {
+    for (int i = 0; i < kBatchBuckets; ++i)
+        if (a.leaf[i] != b.leaf[i] || a.tile[i] != b.tile[i]) return false;
     return true;
+}
+
+template <typename K>
+int batch_grid(Ctx &c, K kernel, size_t shm, int count) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, shm) != hipSuccess || per < 1) per = 1;
+    const long long g = (long long)per * c.num_cu;
+    return (int)(count < g ? count : g);
+}
+
+}  // namespace
+
+bool batched_tune_set(int routine, int bucket, int leaf, int tile) {
+    if (routine < 0 || routine > 3 || bucket < 0 || bucket >= kBatchBuckets) return false;
+    const bool lu = routine >= 2;
+    if (lu ? (leaf != 16 && leaf != 32) : (leaf != 32 && leaf != 64)) return false;
+    if (tile != 32 && tile != 64) return false;
+    std::lock_guard<std::mutex> lk(g_bmu);
+    g_tune[routine].leaf[bucket] = (unsigned char)leaf;
+    g_tune[routine].tile[bucket] = (unsigned char)tile;
+    return true;
+}
+
+bool batched_tune_get(int routine, int bucket, int *leaf, int *tile) {
+    if (routine < 0 || routine > 3 || bucket < 0 || bucket >= kBatchBuckets) return false;
+    std::lock_guard<std::mutex> lk(g_bmu);
+    if (leaf) *leaf = g_tune[routine].leaf[bucket];
+    if (tile) *tile = g_tune[routine].tile[bucket];
+    return true;
+}
+
+void batched_graphs(bool on) {
+    std::lock_guard<std::mutex> lk(g_bmu);
+    g_graphs_on = on;
+}
+
+void batched_release() {
+    std::lock_guard<std::mutex> lk(g_bmu);
+    for (auto &g : g_cache) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = BatchGraph();
+    }
+    for (auto &s : g_cap) {
+        if (s) (void)hipStreamDestroy(s);
+        s = nullptr;
+    }
+}
+
+// The launch sequence of one batched call on stream s: queue reset, size
+// order into the workspace, the persistent kernel.
+template <typename T, bool LU>
+static void batch_sequence(hipStream_t s, int grid, size_t shm, int count, int upper, const int *n, T *const *A,
+                           const int *lda, int *const *ipiv, int *info, int *perm, unsigned *queue,
+                           BatchTune tune) {
+    constexpr int KMAX = LU ? kBatchMaxGe : kBatchMaxSpd;
+    hipLaunchKernelGGL(batch_queue_reset_k, dim3(1), dim3(64), 0, s, queue);
+    hipLaunchKernelGGL(batch_order_k<KMAX>, dim3(1), dim3(1024), 0, s, count, n, perm);
+    if constexpr (LU)
+        hipLaunchKernelGGL(getrf_batched_k<T>, dim3(grid), dim3(256), (unsigned)shm, s, count, n, A, lda, ipiv, info,
+                           (const int *)perm, queue, tune);
+    else
+        hipLaunchKernelGGL(potrf_batched_k<T>, dim3(grid), dim3(256), (unsigned)shm, s, count, upper, n, A, lda,
+                           info, (const int *)perm, queue, tune);
+}
+
+template <typename T, bool LU>
+static void batched_call(Ctx &c, int routine, int count, int upper, const int *n, T *const *A, const int *lda,
+                         int *const *ipiv, int *info) {
+    if (count <= 0) return;
+    // workspace: the size order (count ints), then the queue counter
+    const size_t pbytes = ((size_t)count * sizeof(int) + 255) / 256 * 256;
+    char *ws = (char *)workspace(c, kSlotBatchOrder, pbytes + 256);
+    if (!ws) return;
+    int *perm = (int *)ws;
+    unsigned *queue = (unsigned *)(ws + pbytes);
+    const size_t shm = sizeof(BatchLds<T>);
+    const void *kfn = LU ? (const void *)getrf_batched_k<T> : (const void *)potrf_batched_k<T>;
+    RL_CHECK(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    const int grid = LU ? batch_grid(c, getrf_batched_k<T>, shm, count) : batch_grid(c, potrf_batched_k<T>, shm, count);
+    BatchTune tune;
+    bool graphs;
+    {
+        std::lock_guard<std::mutex> lk(g_bmu);
+        tune = g_tune[routine];
+        graphs = g_graphs_on;
+    }
+    if (!graphs || c.trace) {
+        trace_begin(c, PK_OTHER);
+        batch_sequence<T, LU>(c.stream, grid, shm, count, upper, n, A, lda, ipiv, info, perm, queue, tune);
+        RL_CHECK(hipGetLastError());
+        trace_end(c, PK_OTHER, 0.0, 0.0);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_bmu);
+    BatchGraph *hit = nullptr, *slot = &g_cache[0];
+    for (auto &g : g_cache) {
+        if (g.used && g.device == c.device && g.routine == routine && g.count == count && g.upper == upper &&
+            g.grid == grid && g.n == n && g.A == A && g.lda == lda && g.ipiv == ipiv && g.info == info &&
+            g.ws == ws && same_tune(g.tune, tune)) {
+            hit = &g;
+            break;
+        }
+        if (!g.used || g.stamp < slot->stamp) slot = &g;
+    }
+    if (!hit) {
+        // capture the sequence once on a private stream, keep the executable graph
+        hipStream_t &cap = g_cap[c.device];
+        if (!cap) RL_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        if (!cap) return;
+        hipGraph_t graph = nullptr;
+        RL_CHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        batch_sequence<T, LU>(cap, grid, shm, count, upper, n, A, lda, ipiv, info, perm, queue, tune);
+        RL_CHECK(hipGetLastError());
+        RL_CHECK(hipStreamEndCapture(cap, &graph));
+        if (!graph) return;
+        hipGraphExec_t exec = nullptr;
+        RL_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(graph);
+        if (!exec) return;
+        if (slot->exec) (void)hipGraphExecDestroy(slot->exec);
+        *slot = BatchGraph();
+        slot->used = true;
+        slot->device = c.device; slot->routine = routine; slot->count = count; slot->upper = upper;
+        slot->grid = grid;
+        slot->n = n; slot->A = A; slot->lda = lda; slot->ipiv = ipiv; slot->info = info; slot->ws = ws;
+        slot->tune = tune;
+        slot->exec = exec;
+        hit = slot;
+    }
+    hit->stamp = ++g_stamp;
+    RL_CHECK(hipGraphLaunch(hit->exec, c.stream));
 }
 
 template <typename T>
 void potrf_batched(Ctx &c, bool upper, int count, const int *n, T *const *A, const int *lda, int *info) {
-    if (count <= 0) return;
-    const int *perm;
-    if (!batch_order<kBatchMaxSpd>(c, count, n, &perm)) return;
-    const size_t shm = sizeof(BatchLds<T>);
-    RL_CHECK(hipFuncSetAttribute((const void *)potrf_batched_k<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)shm));
-    rl_launch(c, potrf_batched_k<T>, dim3(count), dim3(256), (unsigned)shm, count, (int)upper, n, A, lda, info,
-              perm);
-    RL_CHECK(hipGetLastError());
+    batched_call<T, false>(c, std::is_same<T, double>::value ? 0 : 1, count, (int)upper, n, A, lda,
+                           (int *const *)nullptr, info);
 }
 
 template <typename T>
 void getrf_batched(Ctx &c, int count, const int *n, T *const *A, const int *lda, int *const *ipiv, int *info) {
-    if (count <= 0) return;
-    const int *perm;
-    if (!batch_order<kBatchMaxGe>(c, count, n, &perm)) return;
-    const size_t shm = sizeof(BatchLds<T>);
-    RL_CHECK(hipFuncSetAttribute((const void *)getrf_batched_k<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)shm));
-    rl_launch(c, getrf_batched_k<T>, dim3(count), dim3(256), (unsigned)shm, count, n, A, lda, ipiv, info, perm);
-    RL_CHECK(hipGetLastError());
+    batched_call<T, true>(c, std::is_same<T, double>::value ? 2 : 3, count, 0, n, A, lda, ipiv, info);
 }
 
 template void potrf_batched<double>(Ctx &, bool, int, const int *, double *const *, const int *, int *);

@@ -211,6 +211,13 @@ void potrf_batched(Ctx &c, bool upper, int count, const int *n, T *const *A, con
 template <typename T>
 void getrf_batched(Ctx &c, int count, const int *n, T *const *A, const int *lda, int *const *ipiv, int *info);
 void trti2_leaf(Ctx &c, bool lower, bool unit, int t, double *A, long long lda);
+// Per-bucket leaf / tile choices of the batched routines (0 dpotrf, 1 spotrf,
+// 2 dgetrf, 3 sgetrf), graph capture on or off, and release of the captured
+// graphs.
+bool batched_tune_set(int routine, int bucket, int leaf, int tile);
+bool batched_tune_get(int routine, int bucket, int *leaf, int *tile);
+void batched_graphs(bool on);
+void batched_release();
 
 // Mixed precision helpers.
 void scale_spd_f32(Ctx &c, char uplo, long long n, const double *A, long long lda, double *d,

@@ -42,6 +42,15 @@ def test_argument_checks_without_gpu():
     assert _info(L.relapack_dgetrf, 4, -1, 0, 4, 0) == -2
     assert _info(L.relapack_dgetrf, 9, 4, 0, 8, 0) == -4
     assert _info(L.relapack_dgetrf, 0, 5, 0, 1, 0) == 0
+    # batched tuning table: only the offered leaf sizes and tile edges, read back as set
+    assert L.relapack_batched_tune(0, 0, 16, 64) == -3
+    assert L.relapack_batched_tune(2, 0, 64, 64) == -3
+    assert L.relapack_batched_tune(0, 0, 64, 48) == -3
+    assert L.relapack_batched_tune(0, 4, 64, 64) == -2
+    assert L.relapack_batched_tune(5, 0, 64, 64) == -1
+    lf, tl = ctypes.c_int(0), ctypes.c_int(0)
+    assert L.relapack_batched_tune_get(2, 1, ctypes.byref(lf), ctypes.byref(tl)) == 0
+    assert (lf.value, tl.value) in {(16, 32), (16, 64), (32, 32), (32, 64)}
     # the allocation-free LU: same checks, and m above its fixed workspace (32768 rows) is refused
     assert _info(L.relapack_dgetrf_noalloc, -1, 4, 0, 4, 0) == -1
     assert _info(L.relapack_dgetrf_noalloc, 32769, 4, 0, 32769, 0) == -1

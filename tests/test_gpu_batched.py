@@ -269,3 +269,101 @@ def test_batched_size_order_with_illegal_sizes(orc, routine):
             ref, rpiv, _ = orc.getrf(mats[i])
             assert np.array_equal(pivs[i].cpu().numpy()[: ns[i]], rpiv), i
             assert rel_fro(f, ref) <= 1e-9, i
+
+
+@pytest.mark.parametrize("routine,leaf,tile", [("dpotrf", 32, 32), ("dpotrf", 32, 64), ("dpotrf", 64, 32),
+                                               ("spotrf", 32, 32), ("dgetrf", 16, 32), ("dgetrf", 16, 64),
+                                               ("dgetrf", 32, 32), ("sgetrf", 16, 32)])
+def test_batched_every_tuning_choice(orc, routine, leaf, tile):
+    """Each leaf size / tile edge the autotuner may pick, set for every size
+    bucket, against the oracle (the defaults are covered by the tests above);
+    the table is restored afterwards."""
+    saved = [rl.batched_tune_get(routine, b) for b in range(4)]
+    try:
+        for b in range(4):
+            assert rl.batched_tune(routine, b, leaf, tile) == 0
+        single = routine.startswith("s")
+        if routine.endswith("potrf"):
+            sizes = [1, 17, 32, 33, 64, 65, 100, 129, 200, 257, 300, 512]
+            mats = [gen.spd_bbt(n, seed=40 + n) for n in sizes]
+            if single:
+                mats = [a.astype(np.float32).astype(np.float64) for a in mats]
+            got, info = _potrf_batch(mats, single=single)
+            assert (info == 0).all()
+            for a, g in zip(mats, got):
+                n = a.shape[0]
+                ref, _ = orc.potrf(a)
+                tol = 20 * n * U32 if single else 1e-12
+                assert rel_fro(np.tril(g), np.tril(ref)) <= tol, n
+        else:
+            sizes = [1, 15, 16, 17, 32, 33, 64, 65, 100, 129, 200, 256]
+            mats = [gen.general_uniform(n, n, seed=60 + n) for n in sizes]
+            if single:
+                mats = [a.astype(np.float32).astype(np.float64) for a in mats]
+            got, pivs, info = _getrf_batch(mats, single=single)
+            assert (info == 0).all()
+            for a, f, piv in zip(mats, got, pivs):
+                n = a.shape[0]
+                L, U = orc.unpack_lu(f)
+                assert np.abs(L).max() <= 1.0
+                res = np.linalg.norm(orc.apply_ipiv(a, piv) - L @ U) / np.linalg.norm(a)
+                assert res <= 10 * n * (U32 if single else U64), n
+                if not single:
+                    ref, rpiv, _ = orc.getrf(a)
+                    assert np.array_equal(piv, rpiv), n
+                    assert rel_fro(f, ref) <= 1e-9, n
+    finally:
+        for b, (lf, tl) in enumerate(saved):
+            assert rl.batched_tune(routine, b, lf, tl) == 0
+
+
+def test_batched_tune_rejects_values():
+    assert rl.batched_tune("dpotrf", 0, 16, 64) == -3     # 16 is an LU panel width only
+    assert rl.batched_tune("dgetrf", 0, 64, 64) == -3
+    assert rl.batched_tune("dpotrf", 0, 64, 48) == -3
+    assert rl.batched_tune("dpotrf", 4, 64, 64) == -2
+    assert rl.batched_tune(7, 0, 64, 64) == -1
+
+
+@pytest.mark.parametrize("routine", ["potrf", "getrf"])
+def test_batched_graph_replays_match_direct_launches(routine):
+    """The captured graph, replayed several times with other device work and
+    synchronizations in between, gives bit for bit what direct launches give."""
+    import torch
+
+    g = np.random.default_rng(21)
+    count = 900   # more matrices than the persistent grid holds at once
+    ns = g.integers(1, 200 if routine == "potrf" else 120, size=count)
+    mats = [gen.spd_bbt(int(n), seed=int(7000 + i)) if routine == "potrf"
+            else gen.general_uniform(int(n), int(n), seed=int(7000 + i)) for i, n in enumerate(ns)]
+    devs, ptrs, n, lda, info = _dev_batch(mats, [int(x) for x in ns])
+    src = [d.clone() for d in devs]
+    pivs = [torch.zeros(max(int(x), 1), dtype=torch.int32, device="cuda") for x in ns]
+    pptrs = torch.tensor([p.data_ptr() for p in pivs], dtype=torch.int64, device="cuda")
+
+    def call():
+        for d, s in zip(devs, src):
+            d.copy_(s)
+        info.fill_(-99)
+        if routine == "potrf":
+            assert rl.potrf_batched("L", count, n, ptrs, lda, info) == 0
+        else:
+            assert rl.getrf_batched(count, n, ptrs, lda, pptrs, info) == 0
+        torch.cuda.synchronize()
+        return ([to_host(d) for d in devs], [p.cpu().numpy().copy() for p in pivs], info.cpu().numpy().copy())
+
+    rl.batched_graphs(False)
+    try:
+        ref = call()
+    finally:
+        rl.batched_graphs(True)
+    assert (ref[2] == 0).all()
+    for rep in range(4):
+        scratch = torch.randn(1 << 20, device="cuda")   # other work between the replays
+        scratch.mul_(2.0).sum().item()
+        got = call()
+        assert np.array_equal(got[2], ref[2]), rep
+        for a, b in zip(got[0], ref[0]):
+            assert np.array_equal(a, b), rep
+        for a, b in zip(got[1], ref[1]):
+            assert np.array_equal(a, b), rep
