@@ -89,6 +89,22 @@ void relapack_dpotrf(char uplo, int n, double *A, int lda, int *info);
 void relapack_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info);
 
 /*
+ * Look-ahead of the LU recursion (relapack_dgetrf, relapack_sgetrf and the
+ * mixed solves' LU; off by default, on = 1 enables it): at a node whose right
+ * half's update is at most 2.5e11 flops, the right half's leftmost block of
+ * at most 512 columns is updated first and factored on a second stream while
+ * the rest of the update runs on a stream restricted to all but 64 CUs (both
+ * of default priority, created on first use, ordered against the calling
+ * stream by events). Results are bit-identical with it on or off. Measured
+ * on MI355X it is slower (dgetrf n = 16384: 142.0 ms off, 153.3 ms on;
+ * n = 32768: 602.4 against 626.9 ms): the streams overlap, but the split
+ * update on fewer CUs loses as much as the overlap hides, because the block's
+ * factorization, bound by its 16 panels' latency, outlasts the rest of the
+ * update at every node where the update is short enough to split.
+ */
+void relapack_lookahead(int on);
+
+/*
  * relapack_dgetrf without any allocation, for callers that cannot allocate
  * device memory while they run (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc). Same operation, arguments, results

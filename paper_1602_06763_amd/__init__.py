@@ -70,6 +70,7 @@ _SIGS = {
     "relapack_batched_tune": ([_c_int, _c_int, _c_int, _c_int], _c_int),
     "relapack_batched_tune_get": ([_c_int, _c_int, _ip, _ip], _c_int),
     "relapack_batched_graphs": ([_c_int], None),
+    "relapack_lookahead": ([_c_int], None),
     "relapack_trace_enable": ([_c_int], None),
     "relapack_trace_collect": ([_dp, _c_int], _c_int),
     "relapack_plan": ([ctypes.c_char_p, _c_ll, _c_ll, _c_int, _llp, _c_ll], _c_ll),
@@ -417,6 +418,11 @@ def batched_tune_get(routine, bucket: int):
     if r != 0:
         raise ValueError(f"routine {routine!r} / bucket {bucket}: {r}")
     return leaf.value, tile.value
+
+
+def lookahead(on: bool) -> None:
+    """relapack_lookahead: the LU recursion's look-ahead on or off."""
+    lib().relapack_lookahead(1 if on else 0)
 
 
 def batched_graphs(on: bool) -> None:

@@ -33,6 +33,9 @@ struct DevState {
     unsigned long long *trsv_ticket = nullptr;
     unsigned long long trsv_tickets = 0;
     unsigned int trsv_epoch = 0;
+    // LU look-ahead: CU-masked stream pair (created on first use)
+    bool la_tried = false;
+    LaStreams la;
 };
 
 DevState g_dev[kMaxDev];
@@ -172,6 +175,56 @@ unsigned long long *panel_records(Ctx &c, unsigned int *epoch) {
     *epoch = d.panel_epoch;
     d.panel_epoch += kLuLeaf;
     return d.panel_rec;
+}
+
+namespace {
+// off by default: on MI355X it measured slower (dgetrf n = 16384: 142.0 ms
+// off, 153.3 ms on; n = 32768: 602.4 against 626.9 ms), see relapack.h
+bool g_la_on = false;
+}
+
+bool lookahead_enabled() { return g_la_on; }
+void lookahead_enable(bool on) { g_la_on = on; }
+
+// The update of the rest of the right half runs on a stream restricted to
+// all but 64 CUs (logical CU i sits on XCD i mod 8, so the first 64 are 8 per
+// XCD); the block factored ahead runs on an unrestricted stream, so its
+// cooperative panels (up to 64 resident workgroups, one per CU, at
+// m <= 32768) always find the 64 CUs the update leaves free, and its other
+// kernels take the whole chip once the update is done.
+bool lookahead_streams(Ctx &c, LaStreams *out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState &d = g_dev[c.device];
+    if (!d.la_tried) {
+        d.la_tried = true;
+        const int ncu = d.num_cu, small = 64;
+        if (ncu >= 2 * small && ncu <= 1024) {
+            const int words = (ncu + 31) / 32;
+            std::vector<uint32_t> mb(words, 0u);
+            for (int i = small; i < ncu; ++i) mb[i / 32] |= 1u << (i % 32);
+            hipStream_t a = nullptr, b = nullptr;
+            bool ok = hipStreamCreateWithFlags(&a, hipStreamNonBlocking) == hipSuccess &&
+                      hipExtStreamCreateWithCUMask(&b, (uint32_t)words, mb.data()) == hipSuccess;
+            for (int e = 0; ok && e < 3; ++e)
+                ok = hipEventCreateWithFlags(&d.la.ev[e], hipEventDisableTiming) == hipSuccess;
+            if (ok) {
+                d.la.small = a;
+                d.la.big = b;
+                d.la.small_cu = ncu;
+                d.la.big_cu = ncu - small;
+            } else {
+                if (a) (void)hipStreamDestroy(a);
+                if (b) (void)hipStreamDestroy(b);
+                for (auto &e : d.la.ev) {
+                    if (e) (void)hipEventDestroy(e);
+                    e = nullptr;
+                }
+                (void)hipGetLastError();
+            }
+        }
+    }
+    *out = d.la;
+    return d.la.small != nullptr;
 }
 
 TrsvWork trsv_work(Ctx &c, long long m, int nb, int launches, long long row_words, int tickets_per_block) {
@@ -432,6 +485,8 @@ int relapack_batched_tune_get(int routine, int bucket, int *leaf, int *tile) {
 
 void relapack_batched_graphs(int on) { batched_graphs(on != 0); }
 
+void relapack_lookahead(int on) { lookahead_enable(on != 0); }
+
 int relapack_set_stream(void *stream) {
     ctx().stream = (hipStream_t)stream;
     return 0;
@@ -457,6 +512,10 @@ void relapack_finalize(void) {
         if (d.rowsrc) (void)hipFree(d.rowsrc);
         if (d.trsv_x) (void)hipFree(d.trsv_x);
         if (d.trsv_ticket) (void)hipFree(d.trsv_ticket);
+        if (d.la.small) (void)hipStreamDestroy(d.la.small);
+        if (d.la.big) (void)hipStreamDestroy(d.la.big);
+        for (auto &e : d.la.ev)
+            if (e) (void)hipEventDestroy(e);
         for (int s = 0; s < kScratchSlots; ++s)
             if (d.slot[s]) (void)hipFree(d.slot[s]);
         d = DevState();

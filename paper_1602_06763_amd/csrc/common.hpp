@@ -102,7 +102,25 @@ struct Ctx {
     // set only during a caller-free call: workspace comes from here, and the
     // left-side solves avoid the single-launch TRSV (which needs its own buffers)
     FixedWs *fixed = nullptr;
+    // LU look-ahead in progress: the block [la_c0, la_c0 + la_w) is being
+    // factored on the small CU-masked stream; when it is done, the call
+    // returns to la_main after waiting for la_ev_big (the rest of the update)
+    long long la_c0 = -1, la_w = 0;
+    hipStream_t la_main = nullptr;
+    hipEvent_t la_ev_big = nullptr, la_ev_small = nullptr;
+    int la_main_cu = 0;
 };
+
+// Two streams of one device restricted to disjoint CU sets (default
+// priority) for the LU look-ahead, with the events that order them.
+struct LaStreams {
+    hipStream_t small = nullptr, big = nullptr;
+    int small_cu = 0, big_cu = 0;
+    hipEvent_t ev[3] = {};
+};
+bool lookahead_streams(Ctx &c, LaStreams *out);   // false: not available on this device
+bool lookahead_enabled();
+void lookahead_enable(bool on);
 
 Ctx &ctx();
 void ensure_device(Ctx &c);

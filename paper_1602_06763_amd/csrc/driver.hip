@@ -62,6 +62,28 @@ template void potrf_rec<float>(Ctx &, Mfma, char, long long, float *, long long,
 // the same order, so the result is the same as with the recursion's order
 // at every level.
 // ---------------------------------------------------------------------------
+// Look-ahead (a batch node whose right half's update is not too large): the
+// right half's leftmost block of at most kLaswpBlock columns, B1, is updated
+// first, and B1 is factored on a stream restricted to a small CU set while
+// the rest of the right half's update runs on the other CUs; the call returns
+// to its own stream once B1 is done (la_join). B1's kernels touch only B1's
+// columns (its interchanges stay inside its block until its parent's batch),
+// and the rest of the update reads only the left half and writes only the
+// other columns, so the two are independent. Above kLaMaxFlops the update
+// alone would outlast B1 on the reduced CU set, and splitting it only slows it.
+constexpr double kLaMaxFlops = 2.5e11;
+
+static void la_join(Ctx &c, long long c0, long long w) {
+    if (c.la_c0 != c0 || c.la_w != w) return;
+    RL_CHECK(hipEventRecord(c.la_ev_small, c.stream));
+    c.stream = c.la_main;
+    c.num_cu = c.la_main_cu;
+    RL_CHECK(hipStreamWaitEvent(c.stream, c.la_ev_small, 0));
+    RL_CHECK(hipStreamWaitEvent(c.stream, c.la_ev_big, 0));
+    c.la_c0 = -1;
+    c.la_w = 0;
+}
+
 template <typename T>
 static void getrf_rec(Ctx &c, Mfma mode, long long m, long long ncols, T *A, long long lda, int *ipiv,
                       long long c0, long long w, long long blk0, long long blk1, int depth) {
@@ -69,6 +91,7 @@ static void getrf_rec(Ctx &c, Mfma mode, long long m, long long ncols, T *A, lon
     if (w <= leaf) {
         getf2_panel<T>(c, m, (int)w, A, lda, c0, ipiv);
         laswp_leaf<T>(c, A, lda, c0, (int)w, m, ipiv, blk0, blk1);
+        la_join(c, c0, w);
         return;
     }
     const long long w1 = split_size(w), w2 = w - w1;
@@ -85,13 +108,49 @@ static void getrf_rec(Ctx &c, Mfma mode, long long m, long long ncols, T *A, lon
     T *A12 = A + c0 + (c0 + w1) * lda;
     T *A21 = A + (c0 + w1) + c0 * lda;
     T *A22 = A + (c0 + w1) + (c0 + w1) * lda;
-    trsm<T, T>(c, mode, 'L', 'L', 'N', 'U', w1, w2, A11, lda, A12, lda);
-    gemm<T, T, T>(c, mode, 'N', 'N', 0, m - c0 - w1, w2, w1, -1.0, A21, lda, A12, lda, 1.0, A22, lda);
+    long long b1w = w2;   // the right half's leftmost block of at most kLaswpBlock columns
+    while (b1w > kLaswpBlock) b1w = split_size(b1w);
+    const long long rw = w2 - b1w;
+    LaStreams las;
+    const bool la = batch && c.lu_batch && !c.plan && !c.fixed && c.la_c0 < 0 && rw > 0 && lookahead_enabled() &&
+                    2.0 * (double)(m - c0 - w1) * (double)rw * (double)w1 <= kLaMaxFlops &&
+                    (m - c0 - w1 + kPanelRows - 1) / kPanelRows <= 64 && lookahead_streams(c, &las);
+    if (!la) {
+        trsm<T, T>(c, mode, 'L', 'L', 'N', 'U', w1, w2, A11, lda, A12, lda);
+        gemm<T, T, T>(c, mode, 'N', 'N', 0, m - c0 - w1, w2, w1, -1.0, A21, lda, A12, lda, 1.0, A22, lda);
+    } else {
+        // B1's columns on the calling stream
+        trsm<T, T>(c, mode, 'L', 'L', 'N', 'U', w1, b1w, A11, lda, A12, lda);
+        gemm<T, T, T>(c, mode, 'N', 'N', 0, m - c0 - w1, b1w, w1, -1.0, A21, lda, A12, lda, 1.0, A22, lda);
+    }
     const int *inv2 = batch ? lu_inverse(c, 2 * depth + 1, c0 + w1, m) : nullptr;
+    if (la) {
+        // fork: the rest of the update on the large CU set, B1 on the small one
+        const hipStream_t main = c.stream;
+        const int main_cu = c.num_cu;
+        RL_CHECK(hipEventRecord(las.ev[0], main));
+        RL_CHECK(hipStreamWaitEvent(las.big, las.ev[0], 0));
+        RL_CHECK(hipStreamWaitEvent(las.small, las.ev[0], 0));
+        c.stream = las.big;
+        c.num_cu = las.big_cu;
+        trsm<T, T>(c, mode, 'L', 'L', 'N', 'U', w1, rw, A11, lda, A12 + b1w * lda, lda);
+        gemm<T, T, T>(c, mode, 'N', 'N', 0, m - c0 - w1, rw, w1, -1.0, A21, lda, A12 + b1w * lda, lda, 1.0,
+                      A22 + b1w * lda, lda);
+        RL_CHECK(hipEventRecord(las.ev[1], las.big));
+        c.stream = las.small;
+        c.num_cu = las.small_cu;
+        c.la_c0 = c0 + w1;
+        c.la_w = b1w;
+        c.la_main = main;
+        c.la_main_cu = main_cu;
+        c.la_ev_big = las.ev[1];
+        c.la_ev_small = las.ev[2];
+    }
     c.level++;
     getrf_rec<T>(c, mode, m, ncols, A, lda, ipiv, c0 + w1, w2, rb0, rb1, depth + 1);
     c.level--;
     if (batch) laswp_batch<T>(c, A, lda, c0, w1, c0 + w1, m, inv2, w2);
+    la_join(c, c0, w);
 }
 
 template <typename T>
@@ -112,7 +171,13 @@ void getrf_top(Ctx &c, Mfma mode, long long m, long long n, T *A, long long lda,
         lu_track_begin(c, m);
         if (n > mn) inv0 = lu_inverse(c, 2 * kLaswpDepth, 0, m);   // of the identity
     }
+    c.la_c0 = -1;
     getrf_rec<T>(c, mode, m, n, A, lda, ipiv, 0, mn, 0, n, 0);
+    if (c.la_c0 >= 0) {   // never left pending; restore the calling stream regardless
+        c.stream = c.la_main;
+        c.num_cu = c.la_main_cu;
+        c.la_c0 = -1;
+    }
     if (c.lu_batch && n > mn) laswp_batch<T>(c, A, lda, mn, n - mn, 0, m, inv0, mn);
     c.lu_tracked = c.lu_batch && !c.plan;
     c.lu_batch = false;

@@ -139,3 +139,27 @@ def test_tall_exact_dyadic():
     ipiv_ref, rows = gen.exact_lu_pivots(perm, n)
     assert info == 0 and np.array_equal(piv, ipiv_ref)
     assert np.array_equal(np.tril(f, -1) + np.eye(m, n), lo[rows]) and np.array_equal(np.triu(f[:n]), up)
+
+
+@pytest.mark.parametrize("m,n", [(2048, 2048), (3000, 2600), (4096, 4096), (2600, 3000)])
+def test_lookahead_changes_nothing(m, n):
+    """The look-ahead (a block factored on its own CU set while the rest of the
+    update runs) reorders launches across streams, never arithmetic: ipiv and
+    the factors are bit-identical with it on and off."""
+    import torch
+
+    torch.cuda.set_device(0)
+    rl.set_stream(torch.cuda.current_stream())
+    a = gen.general_uniform(m, n, seed=m + n)
+    out = []
+    for on in (False, True):
+        rl.lookahead(on)
+        try:
+            A, piv = to_dev(a), ipiv_dev(min(m, n))
+            assert rl.getrf(A, piv) == 0
+            torch.cuda.synchronize()
+            out.append((to_host(A), piv.cpu().numpy()))
+        finally:
+            rl.lookahead(False)
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][0], out[1][0])
