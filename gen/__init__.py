@@ -322,3 +322,63 @@ def batch_seeds(count: int, seed: int) -> np.ndarray:
     """Per-matrix seeds of a batch: ``count`` 62-bit integers from the
     generator of ``seed + 1`` (the sizes use ``seed`` itself)."""
     return rng(seed + 1).integers(0, 2**62, size=count, dtype=np.int64)
+
+
+# -- complex inputs (the c/z instances) ------------------------------------------
+
+def hpd_bbh(n: int, seed: int = 0) -> np.ndarray:
+    """Hermitian positive definite A = B·Bᴴ + n·I, B with real and imaginary
+    parts i.i.d. uniform[-1, 1] (one ``uniform`` call of shape (2, n, n): real
+    parts, then imaginary parts). Lower triangle mirrored (conjugated) so that
+    A is exactly Hermitian with a real diagonal."""
+    g = rng(seed)
+    d = g.uniform(-1.0, 1.0, size=(2, n, n))
+    b = d[0] + 1j * d[1]
+    a = b @ b.conj().T
+    a = np.tril(a) + np.tril(a, -1).conj().T
+    a[np.diag_indices(n)] = a[np.diag_indices(n)].real + float(n)
+    return np.asfortranarray(a, dtype=np.complex128)
+
+
+def general_complex(m: int, n: int | None = None, seed: int = 0) -> np.ndarray:
+    """A (m×n) with real and imaginary parts i.i.d. uniform[-1, 1] (one
+    ``uniform`` call of shape (2, n, m), transposed)."""
+    if n is None:
+        n = m
+    d = rng(seed).uniform(-1.0, 1.0, size=(2, n, m))
+    return np.asfortranarray((d[0] + 1j * d[1]).T, dtype=np.complex128)
+
+
+def exact_zchol(n: int, seed: int = 0):
+    """A = L·Lᴴ with L lower triangular, a real diagonal in {1, 2, 4, 8} and
+    Gaussian integers with parts in [-3, 3] below it: every step of the
+    Cholesky is exact in binary64, so L comes back bit for bit. Returns (A, L)."""
+    g = rng(seed)
+    lo = np.tril(g.integers(-3, 4, size=(n, n)) + 1j * g.integers(-3, 4, size=(n, n)), -1)
+    lo[np.diag_indices(n)] = 2.0 ** g.integers(0, 4, size=n)
+    a = lo @ lo.conj().T
+    return np.asfortranarray(a, dtype=np.complex128), np.asfortranarray(lo, dtype=np.complex128)
+
+
+_ZL_VALUES = np.array([0, 0.5, -0.5, 0.25, -0.25, 0.5j, -0.5j, 0.25j, -0.25j,
+                       0.25 + 0.25j, 0.25 - 0.25j, -0.25 + 0.25j, -0.25 - 0.25j])
+
+
+def exact_zlu(n: int, seed: int = 0):
+    """A = Pᵀ·L·U with a random permutation P, L unit lower with dyadic
+    Gaussian entries (|re| + |im| <= 1/2) and U upper with Gaussian integers
+    in [-4, 4] and a real diagonal in ±{1, 2, 4, 8}: partial pivoting by
+    |re| + |im| picks exactly P and every step is exact. Returns
+    (A, perm, L, U) with row i of A = row perm[i] of L·U, as ``exact_lu``, so
+    ``exact_lu_pivots`` gives the expected ipiv and row order. Draw order:
+    perm, L's entries, U's upper entries (real, then imaginary parts), U's
+    diagonal signs, then its exponents."""
+    g = rng(seed)
+    perm = g.permutation(n)
+    lo = np.tril(_ZL_VALUES[g.integers(0, len(_ZL_VALUES), size=(n, n))], -1) + np.eye(n)
+    up = np.triu(g.integers(-4, 5, size=(n, n)) + 1j * g.integers(-4, 5, size=(n, n)), 1)
+    up = up + np.diag(g.choice([-1, 1], size=n) * 2.0 ** g.integers(0, 4, size=n))
+    lu = lo @ up
+    a = lu[perm, :]
+    return (np.asfortranarray(a, dtype=np.complex128), perm, np.asfortranarray(lo, dtype=np.complex128),
+            np.asfortranarray(up, dtype=np.complex128))

@@ -32,6 +32,15 @@ Parity status of each function (what pins it is in ``tests/test_oracle_pins.py``
                        multiplication, identity, strict other triangle untouched.
 * ``potri``            pinned: exact integer inverse of A = L·Lᵀ with unit
                        bidiagonal L, residual bound ‖A·X − I‖.
+* ``zpotrf``           pinned: exact Gaussian-integer factors with a
+                       power-of-two diagonal, a hand-checked 2×2 closed form,
+                       real symmetric inputs (equal to ``potrf`` bit for bit),
+                       upper = conjugate transpose of lower, failure index,
+                       residual bound.
+* ``zgetrf``           pinned: exact dyadic Gaussian P·L·U, a hand-checked
+                       column where |re| + |im| and |z| pick different rows,
+                       real inputs (same pivots as ``getrf``), zero pivots,
+                       residual bound and every multiplier's modulus <= √2.
 """
 from __future__ import annotations
 
@@ -92,6 +101,10 @@ def lib() -> ctypes.CDLL:
         L.oracle_dlauum.restype = None
         L.oracle_set_threads.argtypes = [c_int]
         L.oracle_set_threads.restype = None
+        L.oracle_zpotrf.argtypes = [c_char, c_int, dp, c_int]
+        L.oracle_zpotrf.restype = c_int
+        L.oracle_zgetrf.argtypes = [c_int, c_int, dp, c_int, ip]
+        L.oracle_zgetrf.restype = c_int
         L.oracle_get_threads.argtypes = []
         L.oracle_get_threads.restype = c_int
         _lib = L
@@ -137,6 +150,29 @@ def getrf(a):
     m, n = a.shape
     ipiv = np.zeros(max(min(m, n), 1), dtype=np.int32)
     info = lib().oracle_dgetrf(m, n, _dp(a), max(m, 1), _ip(ipiv))
+    return a, ipiv[: min(m, n)], int(info)
+
+
+def _c128(a):
+    return np.array(a, dtype=np.complex128, order="F", copy=True)
+
+
+def zpotrf(a, uplo: str = "L"):
+    """Cholesky of a copy of the Hermitian ``a`` (complex, A = L·Lᴴ or Uᴴ·U);
+    returns (factored array, info)."""
+    a = _c128(a)
+    n = a.shape[0]
+    info = lib().oracle_zpotrf(uplo.encode(), n, _dp(a), max(n, 1))
+    return a, int(info)
+
+
+def zgetrf(a):
+    """Partial-pivoting LU of a copy of the complex ``a`` (m×n), pivots by
+    |re| + |im|; returns (LU array, ipiv (1-based), info)."""
+    a = _c128(a)
+    m, n = a.shape
+    ipiv = np.zeros(max(min(m, n), 1), dtype=np.int32)
+    info = lib().oracle_zgetrf(m, n, _dp(a), max(m, 1), _ip(ipiv))
     return a, ipiv[: min(m, n)], int(info)
 
 

@@ -496,3 +496,125 @@ double oracle_backward_error(char sym, int n, int nrhs, const double *A, int lda
     }
     return worst;
 }
+
+/* ---------------------------------------------------------------------------
+ * Complex instances (the c/z types of the collection, Sec. 5): storage is
+ * LAPACK's, each element a (real, imaginary) pair of doubles, column-major.
+ * The arithmetic is written out in real operations so that its order is
+ * visible:
+ *   product   (a·b) = (a.re·b.re − a.im·b.im, a.re·b.im + a.im·b.re)
+ *   quotient  a / p = (a·conj(p)) / (p.re² + p.im²), each part divided
+ *   pivot size cabs1(z) = |z.re| + |z.im| (LAPACK's izamax rule)
+ * --------------------------------------------------------------------------- */
+typedef struct { double re, im; } zel;
+
+#define ZAT(A, lda, i, j) ((A)[(size_t)(j) * (size_t)(lda) + (size_t)(i)])
+
+static zel zmul(zel a, zel b)
+{
+    zel r;
+    const double p1 = a.re * b.re, p2 = a.im * b.im, p3 = a.re * b.im, p4 = a.im * b.re;
+    r.re = p1 - p2;
+    r.im = p3 + p4;
+    return r;
+}
+
+static zel zconj(zel a) { a.im = -a.im; return a; }
+
+static zel zsub(zel a, zel b) { zel r; r.re = a.re - b.re; r.im = a.im - b.im; return r; }
+
+static zel zdiv(zel a, zel p)
+{
+    const double d1 = p.re * p.re, d2 = p.im * p.im;
+    const double den = d1 + d2;
+    const zel q = zmul(a, zconj(p));
+    zel r;
+    r.re = q.re / den;
+    r.im = q.im / den;
+    return r;
+}
+
+static double cabs1(zel z) { return fabs(z.re) + fabs(z.im); }
+
+/*
+ * Cholesky of a Hermitian positive definite matrix (xpotrf, complex):
+ * uplo = 'L': A = L·Lᴴ, L overwrites the lower triangle; uplo = 'U':
+ * A = Uᴴ·U, U overwrites the upper triangle. Only the real part of a
+ * diagonal entry is read; the diagonal of the factor is real (imaginary part
+ * written as 0). Step k: if re(a_kk) is not > 0 (NaN included) return k+1
+ * with a_kk left as it was; else l_kk = sqrt(re(a_kk)), the rest of column
+ * (row) k is divided by it, and the trailing triangle takes
+ * a_ij −= l_ik·conj(l_jk) (lower) or a_ij −= conj(u_ki)·u_kj (upper).
+ */
+int oracle_zpotrf(char uplo, int n, double *Ad, int lda)
+{
+    zel *A = (zel *)Ad;
+    const int lower = is_lower(uplo);
+    for (int k = 0; k < n; ++k) {
+        const double akk = ZAT(A, lda, k, k).re;
+        if (!(akk > 0.0)) return k + 1;
+        const double lkk = sqrt(akk);
+        ZAT(A, lda, k, k).re = lkk;
+        ZAT(A, lda, k, k).im = 0.0;
+        for (int i = k + 1; i < n; ++i) {
+            zel *e = lower ? &ZAT(A, lda, i, k) : &ZAT(A, lda, k, i);
+            e->re = e->re / lkk;
+            e->im = e->im / lkk;
+        }
+#pragma omp parallel for schedule(static)
+        for (int j = k + 1; j < n; ++j) {
+            if (lower) {
+                const zel cjk = zconj(ZAT(A, lda, j, k));
+                for (int i = j; i < n; ++i) ZAT(A, lda, i, j) = zsub(ZAT(A, lda, i, j), zmul(ZAT(A, lda, i, k), cjk));
+            } else {
+                const zel ukj = ZAT(A, lda, k, j);
+                for (int i = k + 1; i <= j; ++i)
+                    ZAT(A, lda, i, j) = zsub(ZAT(A, lda, i, j), zmul(zconj(ZAT(A, lda, k, i)), ukj));
+            }
+        }
+    }
+    return 0;
+}
+
+/*
+ * LU with partial pivoting of a complex m×n matrix (xgetrf, complex): as
+ * oracle_dgetrf with the pivot the first row maximizing cabs1(a_ik) (a NaN
+ * never wins), the column below divided by the pivot, and the rank-1 update
+ * a_ij −= a_ik·a_kj. A pivot with both parts zero is exactly zero: no swap,
+ * no division, info records the first such column.
+ */
+int oracle_zgetrf(int m, int n, double *Ad, int lda, int *ipiv)
+{
+    zel *A = (zel *)Ad;
+    int info = 0;
+    const int mn = m < n ? m : n;
+    for (int k = 0; k < mn; ++k) {
+        int p = k;
+        double best = -1.0;
+        for (int i = k; i < m; ++i) {
+            const double v = cabs1(ZAT(A, lda, i, k));
+            if (v > best) { best = v; p = i; }
+        }
+        ipiv[k] = p + 1;
+        const zel ap = ZAT(A, lda, p, k);
+        if (ap.re != 0.0 || ap.im != 0.0) {
+            if (p != k) {
+                for (int j = 0; j < n; ++j) {
+                    const zel t = ZAT(A, lda, k, j);
+                    ZAT(A, lda, k, j) = ZAT(A, lda, p, j);
+                    ZAT(A, lda, p, j) = t;
+                }
+            }
+            const zel piv = ZAT(A, lda, k, k);
+            for (int i = k + 1; i < m; ++i) ZAT(A, lda, i, k) = zdiv(ZAT(A, lda, i, k), piv);
+        } else if (info == 0) {
+            info = k + 1;
+        }
+#pragma omp parallel for schedule(static)
+        for (int j = k + 1; j < n; ++j) {
+            const zel ukj = ZAT(A, lda, k, j);
+            for (int i = k + 1; i < m; ++i) ZAT(A, lda, i, j) = zsub(ZAT(A, lda, i, j), zmul(ZAT(A, lda, i, k), ukj));
+        }
+    }
+    return info;
+}

@@ -482,3 +482,101 @@ def test_potri_residual(orc):
     assert np.abs(a @ full - np.eye(n)).max() <= 10 * n * U64 * np.abs(a).sum(1).max() * np.abs(full).sum(1).max()
     _, info = orc.potri(-a, "L")
     assert info == 1
+
+
+# ---- complex instances (c/z types) --------------------------------------------------
+
+U64C = 2.0 ** -53
+
+
+@pytest.mark.parametrize("n", [1, 5, 33, 120])
+def test_zpotrf_exact_gaussian_integer_factor(orc, n):
+    a, lo = gen.exact_zchol(n, seed=n)
+    f, info = orc.zpotrf(a, "L")
+    assert info == 0
+    assert np.array_equal(np.tril(f), lo)
+    # upper: A = Uᴴ·U with U = Lᴴ, the strict lower triangle never touched
+    s = a.copy(order="F")
+    s[np.tril_indices(n, -1)] = np.nan
+    f, info = orc.zpotrf(s, "U")
+    assert info == 0 and np.array_equal(np.triu(f), lo.conj().T)
+    assert np.isnan(f[np.tril_indices(n, -1)]).all()
+
+
+def test_zpotrf_2x2_closed_form(orc):
+    # A = [[4, conj(b)], [b, 6]], b = 2+2i: l11 = 2, l21 = b/2 = 1+i, l22 = sqrt(6 - |b|²/4) = 2
+    a = np.array([[4.0, 2 - 2j], [2 + 2j, 6.0]], dtype=np.complex128, order="F")
+    f, info = orc.zpotrf(a, "L")
+    assert info == 0
+    assert np.array_equal(np.tril(f), np.array([[2, 0], [1 + 1j, 2]], dtype=np.complex128))
+
+
+def test_zpotrf_real_input_is_the_real_cholesky(orc):
+    a = gen.spd_bbt(70, seed=3)
+    f, info = orc.zpotrf(a.astype(np.complex128), "L")
+    fr, rinfo = orc.potrf(a, "L")
+    assert info == rinfo == 0
+    assert np.array_equal(np.tril(f).real, np.tril(fr)) and not np.tril(f).imag.any()
+
+
+def test_zpotrf_residual_and_failure(orc):
+    n = 150
+    a = gen.hpd_bbh(n, seed=1)
+    f, info = orc.zpotrf(a, "L")
+    lo = np.tril(f)
+    assert info == 0
+    assert np.linalg.norm(a - lo @ lo.conj().T) <= 10 * n * U64C * np.linalg.norm(a)
+    assert not np.diag(lo).imag.any() and (np.diag(lo).real > 0).all()
+    bad = a.copy(order="F")
+    bad[40, 40] = -1.0e4
+    _, info = orc.zpotrf(bad, "L")
+    assert info == 41
+
+
+@pytest.mark.parametrize("n", [1, 6, 40, 100])
+def test_zgetrf_exact_dyadic(orc, n):
+    a, perm, lo, up = gen.exact_zlu(n, seed=n)
+    f, ipiv, info = orc.zgetrf(a)
+    assert info == 0
+    ipiv_ref, rows = gen.exact_lu_pivots(perm, n)
+    assert np.array_equal(ipiv, ipiv_ref)
+    assert np.array_equal(np.tril(f, -1) + np.eye(n), lo[rows]) and np.array_equal(np.triu(f), up)
+
+
+def test_zgetrf_pivot_rule_is_re_plus_im(orc):
+    # |3| = 3 > |2+2i| = 2.83, but |re| + |im| picks 2+2i (LAPACK's izamax)
+    a = np.array([[3.0, 1.0], [2 + 2j, 1.0]], dtype=np.complex128, order="F")
+    _, ipiv, _ = orc.zgetrf(a)
+    assert ipiv[0] == 2
+    # a tie in |re| + |im| (3 against 1.5+1.5i) keeps the first row
+    a = np.array([[3.0, 1.0], [1.5 + 1.5j, 1.0]], dtype=np.complex128, order="F")
+    _, ipiv, _ = orc.zgetrf(a)
+    assert ipiv[0] == 1
+
+
+def test_zgetrf_real_input_and_zero_pivot(orc):
+    a = gen.general_uniform(90, 90, seed=4)
+    f, ipiv, info = orc.zgetrf(a.astype(np.complex128))
+    fr, ipr, infor = orc.getrf(a)
+    assert info == infor == 0 and np.array_equal(ipiv, ipr)
+    assert np.abs(f.imag).max() == 0.0
+    assert np.linalg.norm(f.real - fr) <= 1e-13 * np.linalg.norm(fr)
+    z = gen.general_complex(30, 30, seed=5)
+    z[:, 7] = 0.0
+    _, _, info = orc.zgetrf(z)
+    assert info == 8
+
+
+def test_zgetrf_residual(orc):
+    m, n = 160, 120
+    a = gen.general_complex(m, n, seed=6)
+    f, ipiv, info = orc.zgetrf(a)
+    assert info == 0
+    k = min(m, n)
+    lo = np.tril(f[:, :k], -1) + np.eye(m, k)
+    up = np.triu(f[:k, :])
+    # |re| + |im| of every candidate is at most the pivot's, so
+    # |l| <= (|re| + |im| of a) / |p| <= √2 (the modulus bound of izamax pivoting)
+    assert np.abs(lo).max() <= np.sqrt(2.0) * (1 + 1e-15)
+    pa = orc.apply_ipiv(a, ipiv)
+    assert np.linalg.norm(pa - lo @ up) <= 10 * n * U64C * np.linalg.norm(a)
