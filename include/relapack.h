@@ -186,6 +186,48 @@ void relapack_dgesv_mixed(int n, int nrhs, const double *A, int lda, int *ipiv, 
  */
 void relapack_mixed_last(int *sweeps, int *gmres_from, int *gmres_sweeps, int *gmres_steps);
 
+/* ---- complex instances (the c/z types of Sec. 5) ------------------------- */
+
+/*
+ * Complex Cholesky (xpotrf for complex types; Sec. 5 lists every routine of
+ * the collection in the four types s, d, c, z): A Hermitian positive
+ * definite, uplo 'L': A = L·Lᴴ; 'U': A = Uᴴ·U; the factor overwrites that
+ * triangle, the strict other triangle is neither read nor written. A points
+ * to LAPACK's complex storage: n×n (re, im) pairs of doubles (z) or floats
+ * (c), column-major, lda >= max(1, n) elements. Only the real part of a
+ * diagonal entry is read; the factor's diagonal is real (its imaginary parts
+ * written as 0). info = k > 0: re(a_kk) not > 0 (or NaN) at step k, the
+ * factorization stops there (as relapack_dpotrf). Same recursion as the real
+ * routine, its products C -= A·Bᴴ on the matrix cores as four real
+ * products each, leaves of at most 64.
+ * Errors: uplo -1, n -2, lda -4.
+ */
+void relapack_zpotrf(char uplo, int n, void *A, int lda, int *info);
+void relapack_cpotrf(char uplo, int n, void *A, int lda, int *info);
+
+/*
+ * Complex LU with partial pivoting (xgetrf for complex types): A = P·L·U,
+ * the pivot of column k the first row with the largest |re| + |im| (LAPACK's
+ * izamax; a NaN never wins), ipiv (device, min(m, n) ints, 1-based) as
+ * relapack_dgetrf. A: m×n complex (z: pairs of doubles, c: pairs of floats),
+ * column-major. info = k > 0: U(k, k) is exactly zero (both parts), the first
+ * such k; the factorization completes. Leaves are panels of at most 16
+ * columns factored by one workgroup (rows below the diagonal in global
+ * memory), their interchanges applied at once to every other column.
+ * Errors: m -1, n -2, lda -4.
+ */
+void relapack_zgetrf(int m, int n, void *A, int lda, int *ipiv, int *info);
+void relapack_cgetrf(int m, int n, void *A, int lda, int *ipiv, int *info);
+
+/*
+ * C := beta·C + alpha·op(A)·op(B), complex double (pairs of doubles), op 'N',
+ * 'T' or 'C' (conjugate transpose), alpha and beta real: the complex product
+ * the recursion uses, exported for testing. C: m×n.
+ * Errors: transa -1, transb -2, m -3, n -4, k -5, lda -8, ldb -10, ldc -13.
+ */
+void relapack_zgemm(char transa, char transb, int m, int n, int k, double alpha, const void *A, int lda,
+                    const void *B, int ldb, double beta, void *C, int ldc, int *info);
+
 /* ---- building blocks on the recursion's path (FP64 matrix cores) -------- */
 
 /*

@@ -39,6 +39,12 @@ _SIGS = {
     "relapack_dpotrf": ([_c_char, _c_int, _vp, _c_int, _ip], None),
     "relapack_dgetrf": ([_c_int, _c_int, _vp, _c_int, _vp, _ip], None),
     "relapack_dgetrf_noalloc": ([_c_int, _c_int, _vp, _c_int, _vp, _ip], None),
+    "relapack_zpotrf": ([_c_char, _c_int, _vp, _c_int, _ip], None),
+    "relapack_cpotrf": ([_c_char, _c_int, _vp, _c_int, _ip], None),
+    "relapack_zgetrf": ([_c_int, _c_int, _vp, _c_int, _vp, _ip], None),
+    "relapack_cgetrf": ([_c_int, _c_int, _vp, _c_int, _vp, _ip], None),
+    "relapack_zgemm": ([_c_char, _c_char, _c_int, _c_int, _c_int, _c_double, _vp, _c_int, _vp, _c_int,
+                        _c_double, _vp, _c_int, _ip], None),
     "relapack_dpotrs": ([_c_char, _c_int, _c_int, _vp, _c_int, _vp, _c_int, _ip], None),
     "relapack_dgetrs": ([_c_char, _c_int, _c_int, _vp, _c_int, _vp, _vp, _c_int, _ip], None),
     "relapack_dposv_mixed": ([_c_char, _c_int, _c_int, _vp, _c_int, _vp, _c_int, _vp, _c_int, _c_int,
@@ -79,7 +85,7 @@ _SIGS = {
 
 TRACE_FAMILIES = {1: "potf2", 2: "trsm_leaf", 3: "gemm", 4: "syrk", 5: "getf2_panel", 6: "laswp",
                   7: "convert", 8: "residual", 10: "gemm_lowprec", 11: "syrk_lowprec", 12: "gemm128",
-                  13: "trti2", 14: "trmm_leaf", 15: "lauu2"}
+                  13: "trti2", 14: "trmm_leaf", 15: "lauu2", 16: "zgemm", 17: "complex_leaf"}
 
 PREC = {"fp32": 32, "32": 32, 32: 32, "fp16": 16, "16": 16, 16: 16, "bf16": ord("b"), "b": ord("b")}
 
@@ -113,6 +119,7 @@ def _ptr(x) -> int:
 
 
 _F64, _F32, _I32, _I64 = "float64", "float32", "int32", "int64"
+_C128, _C64 = "complex128", "complex64"
 
 
 def _check(t, dtype: str, rows: int, cols: int, ld: int | None = None, what: str = "matrix") -> None:
@@ -215,6 +222,45 @@ def getrf_noalloc(A, ipiv, m: int | None = None, n: int | None = None, lda: int 
     _check_vec(ipiv, _I32, min(m, n), "ipiv")
     info = ctypes.c_int(0)
     lib().relapack_dgetrf_noalloc(m, n, _ptr(A), lda, _ptr(ipiv), ctypes.byref(info))
+    return info.value
+
+
+def zpotrf(A, uplo: str = "L", n: int | None = None, lda: int | None = None) -> int:
+    """relapack_zpotrf (complex128 tensor) or relapack_cpotrf (complex64)."""
+    n = A.shape[0] if n is None else n
+    lda = _ld(A, n) if lda is None else lda
+    single = not isinstance(A, int) and str(A.dtype) == "torch.complex64"
+    _check(A, _C64 if single else _C128, n, n, lda, "A")
+    info = ctypes.c_int(0)
+    f = lib().relapack_cpotrf if single else lib().relapack_zpotrf
+    f(_b(uplo), n, _ptr(A), lda, ctypes.byref(info))
+    return info.value
+
+
+def zgetrf(A, ipiv, m: int | None = None, n: int | None = None, lda: int | None = None) -> int:
+    """relapack_zgetrf (complex128 tensor) or relapack_cgetrf (complex64)."""
+    m = A.shape[0] if m is None else m
+    n = A.shape[1] if n is None else n
+    lda = _ld(A, m) if lda is None else lda
+    single = not isinstance(A, int) and str(A.dtype) == "torch.complex64"
+    _check(A, _C64 if single else _C128, m, n, lda, "A")
+    _check_vec(ipiv, _I32, min(m, n), "ipiv")
+    info = ctypes.c_int(0)
+    f = lib().relapack_cgetrf if single else lib().relapack_zgetrf
+    f(m, n, _ptr(A), lda, _ptr(ipiv), ctypes.byref(info))
+    return info.value
+
+
+def zgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc) -> int:
+    """relapack_zgemm on complex128 tensors (or raw addresses)."""
+    ta, tb = str(transa).upper(), str(transb).upper()
+    if k > 0:
+        _check(A, _C128, k if ta != "N" else m, m if ta != "N" else k, lda, "A")
+        _check(B, _C128, n if tb != "N" else k, k if tb != "N" else n, ldb, "B")
+    _check(C, _C128, m, n, ldc, "C")
+    info = ctypes.c_int(0)
+    lib().relapack_zgemm(_b(ta), _b(tb), m, n, k, float(alpha), _ptr(A), lda, _ptr(B), ldb, float(beta), _ptr(C),
+                         ldc, ctypes.byref(info))
     return info.value
 
 
@@ -454,7 +500,7 @@ def trace_enable(on: bool = True) -> None:
 
 
 def trace_collect() -> dict:
-    cap = 16
+    cap = 18
     out = (ctypes.c_double * (4 * cap))()
     if lib().relapack_trace_collect(out, cap) < 0:
         raise RuntimeError("relapack_trace_collect failed")

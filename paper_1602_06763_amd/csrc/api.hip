@@ -465,6 +465,35 @@ int na_call_end(Ctx &c) {
 }
 
 }  // namespace
+
+template <typename R>
+static void zpotrf_call(char uplo, int n, void *A, int lda, int *info) {
+    if (!info) return;
+    if (!is(uplo, 'L') && !is(uplo, 'U')) { *info = -1; return; }
+    if (n < 0) { *info = -2; return; }
+    if (lda < (n > 1 ? n : 1)) { *info = -4; return; }
+    *info = 0;
+    if (n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, true)) { *info = call_end(c); return; }
+    zpotrf_top<R>(c, is(uplo, 'L') ? 'L' : 'U', n, A, lda);
+    *info = call_end(c);
+}
+
+template <typename R>
+static void zgetrf_call(int m, int n, void *A, int lda, int *ipiv, int *info) {
+    if (!info) return;
+    if (m < 0) { *info = -1; return; }
+    if (n < 0) { *info = -2; return; }
+    if (lda < (m > 1 ? m : 1)) { *info = -4; return; }
+    *info = 0;
+    if (m == 0 || n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    zgetrf_top<R>(c, m, n, A, lda, ipiv);
+    *info = call_end(c);
+}
+
 }  // namespace rl
 
 extern "C" {
@@ -547,6 +576,37 @@ void relapack_dgetrf(int m, int n, double *A, int lda, int *ipiv, int *info) {
     if (!call_begin(c, false)) { *info = call_end(c); return; }
     ensure_rowsrc(c, (size_t)m);
     getrf_top<double>(c, Mfma::F64, m, n, A, lda, ipiv);
+    *info = call_end(c);
+}
+
+void relapack_zpotrf(char uplo, int n, void *A, int lda, int *info) { zpotrf_call<double>(uplo, n, A, lda, info); }
+void relapack_cpotrf(char uplo, int n, void *A, int lda, int *info) { zpotrf_call<float>(uplo, n, A, lda, info); }
+void relapack_zgetrf(int m, int n, void *A, int lda, int *ipiv, int *info) {
+    zgetrf_call<double>(m, n, A, lda, ipiv, info);
+}
+void relapack_cgetrf(int m, int n, void *A, int lda, int *ipiv, int *info) {
+    zgetrf_call<float>(m, n, A, lda, ipiv, info);
+}
+
+void relapack_zgemm(char ta, char tb, int m, int n, int k, double alpha, const void *A, int lda, const void *B,
+                    int ldb, double beta, void *C, int ldc, int *info) {
+    if (!info) return;
+    auto op = [](char t) { return is(t, 'N') ? 0 : is(t, 'T') ? 1 : is(t, 'C') ? 2 : -1; };
+    const int oa = op(ta), ob = op(tb);
+    if (oa < 0) { *info = -1; return; }
+    if (ob < 0) { *info = -2; return; }
+    if (m < 0) { *info = -3; return; }
+    if (n < 0) { *info = -4; return; }
+    if (k < 0) { *info = -5; return; }
+    const int nrowa = oa ? k : m, nrowb = ob ? n : k;
+    if (lda < (nrowa > 1 ? nrowa : 1)) { *info = -8; return; }
+    if (ldb < (nrowb > 1 ? nrowb : 1)) { *info = -10; return; }
+    if (ldc < (m > 1 ? m : 1)) { *info = -13; return; }
+    *info = 0;
+    if (m == 0 || n == 0) return;
+    Ctx &c = ctx();
+    if (!call_begin(c, false)) { *info = call_end(c); return; }
+    zgemm_top<double>(c, oa, ob, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
     *info = call_end(c);
 }
 

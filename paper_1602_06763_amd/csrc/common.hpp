@@ -58,7 +58,9 @@ enum PlanKind : int {
     PK_POTF2 = 1, PK_TRSM_LEAF = 2, PK_GEMM = 3, PK_SYRK = 4, PK_GETF2 = 5, PK_LASWP = 6,
     PK_CONVERT = 7, PK_RESID = 8, PK_OTHER = 9, PK_GEMM_LP = 10, PK_SYRK_LP = 11,
     PK_GEMM_BIG = 12,  // FP64 GEMM launches on 128×128 tiles (traced separately from PK_GEMM)
-    PK_TRTI2 = 13, PK_TRMM_LEAF = 14, PK_LAUU2 = 15
+    PK_TRTI2 = 13, PK_TRMM_LEAF = 14, PK_LAUU2 = 15,
+    PK_ZGEMM = 16,   // complex products on the matrix cores
+    PK_ZLEAF = 17    // complex leaves (Cholesky block, triangular-solve leaf, LU panel)
 };
 
 // Workspace that a caller-free entry point brings in from a fixed device
@@ -229,6 +231,15 @@ void potrf_batched(Ctx &c, bool upper, int count, const int *n, T *const *A, con
 template <typename T>
 void getrf_batched(Ctx &c, int count, const int *n, T *const *A, const int *lda, int *const *ipiv, int *info);
 void trti2_leaf(Ctx &c, bool lower, bool unit, int t, double *A, long long lda);
+// Complex instances (complex.hip): A and C point to interleaved (re, im)
+// pairs of R; ops 0 = N, 1 = T, 2 = C.
+template <typename R>
+void zpotrf_top(Ctx &c, char uplo, long long n, void *A, long long lda);
+template <typename R>
+void zgetrf_top(Ctx &c, long long m, long long n, void *A, long long lda, int *ipiv);
+template <typename R>
+void zgemm_top(Ctx &c, int opa, int opb, long long m, long long n, long long k, double alpha, const void *A,
+               long long lda, const void *B, long long ldb, double beta, void *C, long long ldc);
 // Per-bucket leaf / tile choices of the batched routines (0 dpotrf, 1 spotrf,
 // 2 dgetrf, 3 sgetrf), graph capture on or off, and release of the captured
 // graphs.

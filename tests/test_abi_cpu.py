@@ -42,6 +42,15 @@ def test_argument_checks_without_gpu():
     assert _info(L.relapack_dgetrf, 4, -1, 0, 4, 0) == -2
     assert _info(L.relapack_dgetrf, 9, 4, 0, 8, 0) == -4
     assert _info(L.relapack_dgetrf, 0, 5, 0, 1, 0) == 0
+    # complex instances
+    assert _info(L.relapack_zpotrf, b"X", 4, 0, 4) == -1
+    assert _info(L.relapack_cpotrf, b"L", -3, 0, 4) == -2
+    assert _info(L.relapack_zpotrf, b"U", 8, 0, 7) == -4
+    assert _info(L.relapack_zgetrf, -1, 4, 0, 4, 0) == -1
+    assert _info(L.relapack_cgetrf, 4, -1, 0, 4, 0) == -2
+    assert _info(L.relapack_zgetrf, 9, 4, 0, 8, 0) == -4
+    assert _info(L.relapack_zgemm, b"N", b"Q", 2, 2, 2, 1.0, 0, 2, 0, 2, 0.0, 0, 2) == -2
+    assert _info(L.relapack_zgemm, b"C", b"N", 3, 2, 4, 1.0, 0, 3, 0, 4, 0.0, 0, 3) == -8
     # batched tuning table: only the offered leaf sizes and tile edges, read back as set
     assert L.relapack_batched_tune(0, 0, 16, 64) == -3
     assert L.relapack_batched_tune(2, 0, 64, 64) == -3
