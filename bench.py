@@ -232,9 +232,11 @@ def spd_inverse(n: int, stream, reps: int = 3):
 
 def variants(n: int, stream, reps: int = 3):
     """The other instances at the benchmark size: dpotrf with uplo = 'U' on the
-    same SPD input, and the single-precision spotrf / sgetrf (FP32 storage and
-    FP32 matrix cores) on the FP32-rounded inputs; medians of ``reps`` calls
-    after an untimed one, the input restored before each."""
+    same SPD input, the single-precision spotrf / sgetrf (FP32 storage and
+    FP32 matrix cores) on the FP32-rounded inputs, and the complex zpotrf /
+    zgetrf at n = 8192 (the Hermitian and general recipes of ``gen``);
+    medians of ``reps`` calls after an untimed one, the input restored before
+    each."""
     import numpy as np
     import torch
 
@@ -279,6 +281,24 @@ def variants(n: int, stream, reps: int = 3):
     out["sgetrf_tflops"] = round(2.0 * n ** 3 / 3.0 / (ms * 1e-3) / 1e12, 3)
     out["fp32_matrix_peak_tflops"] = PEAK_FP32
     del G0, G
+    torch.cuda.empty_cache()
+    # complex instances at n = 8192 (complex flops counted in real operations:
+    # 4n³/3 for the Cholesky, 8n³/3 for the LU), against the FP64 matrix peak
+    nz = min(n, 8192)
+    Z0 = gen.hpd_bbh_torch(nz, seed=0, device="cuda")
+    Z = Z0.clone()
+    ms = timed(lambda: rl.zpotrf(Z, "L"), Z0, Z)
+    out["complex_n"] = nz
+    out["zpotrf_ms"] = round(ms, 3)
+    out["zpotrf_tflops"] = round(4.0 * nz ** 3 / 3.0 / (ms * 1e-3) / 1e12, 3)
+    del Z0, Z
+    Z0 = gen.general_complex_torch(nz, nz, seed=1, device="cuda")
+    Z = Z0.clone()
+    piv = torch.zeros(nz, dtype=torch.int32, device="cuda")
+    ms = timed(lambda: rl.zgetrf(Z, piv), Z0, Z)
+    out["zgetrf_ms"] = round(ms, 3)
+    out["zgetrf_tflops"] = round(8.0 * nz ** 3 / 3.0 / (ms * 1e-3) / 1e12, 3)
+    del Z0, Z
     torch.cuda.empty_cache()
     return out
 

@@ -382,3 +382,25 @@ def exact_zlu(n: int, seed: int = 0):
     a = lu[perm, :]
     return (np.asfortranarray(a, dtype=np.complex128), perm, np.asfortranarray(lo, dtype=np.complex128),
             np.asfortranarray(up, dtype=np.complex128))
+
+
+def hpd_bbh_torch(n: int, seed: int = 0, device: str = "cuda"):
+    """The draws of ``hpd_bbh`` with A = B·Bᴴ + n·I formed on the device (the
+    product rounds differently from numpy's), lower triangle mirrored,
+    diagonal real; column-major complex128."""
+    import torch
+
+    d = rng(seed).uniform(-1.0, 1.0, size=(2, n, n))
+    b = torch.complex(torch.from_numpy(d[0]), torch.from_numpy(d[1])).to(device)
+    a = b @ b.conj().T.contiguous()
+    a = torch.tril(a) + torch.tril(a, -1).conj().T
+    a.diagonal().copy_(a.diagonal().real + float(n))
+    return a.T.contiguous().T
+
+
+def general_complex_torch(m: int, n: int | None = None, seed: int = 0, device: str = "cuda"):
+    """Same draws as ``general_complex``, placed on the device column-major."""
+    import torch
+
+    a = general_complex(m, n, seed)
+    return torch.from_numpy(np.ascontiguousarray(a.T)).to(device).T

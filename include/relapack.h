@@ -147,7 +147,7 @@ void relapack_dgetrs(char trans, int n, int nrhs, const double *A, int lda, cons
  * and the correction solve. Stops when every column's normwise backward error
  * eta = ||r||inf / (||A||inf·||x||inf + ||b||inf) <= 1e-14.
  * Sweeps: plain refinement (x += M⁻¹r, M the scaled low-precision factors,
- * applied in FP64) while each sweep cuts eta at least fourfold; after that
+ * applied in FP64) while each sweep at least halves eta; after that
  * GMRES-IR: each sweep solves A·d = r by FP64 GMRES left-preconditioned by
  * M⁻¹ (restart 40, inner tolerance 1e-6, at most 200 Arnoldi steps per
  * solve; Carson and Higham's GMRES-based refinement). Refinement stops after

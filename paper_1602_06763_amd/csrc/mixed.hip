@@ -861,8 +861,10 @@ int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const 
         const double *cs = spd ? w.s1 : w.s2;
         hipLaunchKernelGGL(scale_rows_k, dim3(blocks(n), (unsigned)nrhs), dim3(256), 0, c.stream, n, nrhs, cs,
                            w.D, n, X, ldx);
-        // plain refinement while each sweep cuts eta at least fourfold; then
-        // GMRES-IR, until eta stops halving (twice) or the Arnoldi budget is spent
+        // plain refinement while each sweep at least halves eta; then GMRES-IR,
+        // until eta stops halving (twice) or the Arnoldi budget is spent (at
+        // n = 16384 with FP16 factors of a general system, plain sweeps that
+        // cut eta about 2.5-fold reach 1e-14 sooner than GMRES-IR does)
         double prev = INFINITY;
         bool use_gmres = false;
         int gm_left = kGmTotal, slow = 0;
@@ -871,7 +873,7 @@ int mixed_solve(Ctx &c, bool spd, char uplo, long long n, long long nrhs, const 
             eta = residual_eta(c, n, nrhs, w, B, ldb, X, ldx);
             if (eta <= tol) { status = 1; break; }
             if (!(eta == eta)) { status = -31; break; }
-            if (!use_gmres && sweeps >= 2 && eta > 0.25 * prev) {
+            if (!use_gmres && sweeps >= 2 && eta > 0.5 * prev) {
                 gw = gmres_work(c, n, nrhs);
                 if (!gw.V) return -1000 - (int)hipErrorOutOfMemory;
                 use_gmres = true;

@@ -146,15 +146,15 @@ def test_mixed_falls_back_with_its_code(orc, kind, prec, kappa, code):
 
 
 def test_gmres_ir_converges_where_plain_refinement_is_slow(orc):
-    """BF16 LU of a general n = 4096 system at kappa = 1e2: each plain sweep
-    cuts eta by less than 4, so the solve switches to GMRES-IR after the
-    second sweep and converges without the FP64 fallback."""
+    """BF16 LU of a general n = 4096 system at kappa = 1e2: plain sweeps cut
+    eta by less than 2, so the solve switches to GMRES-IR and converges
+    without the FP64 fallback."""
     n = 4096
     a, b, x0 = gen.conditioned(n, 1e2, "general", nrhs=3, seed=2)
     info, it, berr, x = _solve("general", a, b, "bf16")
     st = rl.mixed_last()
     assert info == 0 and it > 0, (it, st)
-    assert st["gmres_from"] == 2 and st["gmres_sweeps"] >= 1 and 0 < st["gmres_steps"] <= 200
+    assert st["gmres_from"] >= 2 and st["gmres_sweeps"] >= 1 and 0 < st["gmres_steps"] <= 200
     _check_solution(orc, a, b, x, x0, 1e2, berr)
 
 
