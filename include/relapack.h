@@ -149,13 +149,15 @@ void relapack_dgetrs(char trans, int n, int nrhs, const double *A, int lda, cons
  * Sweeps: plain refinement (x += M⁻¹r, M the scaled low-precision factors,
  * applied in FP64) while each sweep at least halves eta; after that
  * GMRES-IR: each sweep solves A·d = r by FP64 GMRES left-preconditioned by
- * M⁻¹ (restart 40, inner tolerance 1e-6, at most 200 Arnoldi steps per
- * solve; Carson and Higham's GMRES-based refinement). Refinement stops after
- * 30 sweeps, when eta fails twice to halve under GMRES-IR, or when a GMRES
- * sweep's residual reduction over its first 12 steps, kept up, would not
- * reach 1e-6 within the remaining Arnoldi budget (the preconditioned matrix
- * then has too many scattered eigenvalues, as when kappa times the
- * factorization's unit roundoff is well above 1).
+ * M⁻¹ (restart 40, inner tolerance 1e-6, at most 40 Arnoldi steps per
+ * solve, one restart cycle: a longer refinement costs more than the FP64
+ * solve it replaces; Carson and Higham's GMRES-based refinement).
+ * Refinement stops after 30 sweeps, when eta fails twice to halve under
+ * GMRES-IR, or when a GMRES sweep's average residual reduction per step,
+ * checked from its 12th step on, would not reach 1e-6 within the remaining
+ * Arnoldi budget (the preconditioned matrix then has too many scattered
+ * eigenvalues, as when kappa times the factorization's unit roundoff is well
+ * above 1).
  * iter (host): > 0 refinement sweeps used; < 0 the FP64 path was used
  * instead: -2 a value overflowed when rounded to the low precision (a scaled
  * entry beyond the FP32 range, or a matrix-core operand beyond the FP16/BF16

@@ -540,9 +540,14 @@ static void prepare_correction(Ctx &c, bool spd, char uplo, long long n, long lo
 // right-hand sides run together, each with its own basis and rotations; a
 // column stops once its preconditioned residual has dropped by kGmTol.
 constexpr int kGmMax = 40;        // Arnoldi steps per sweep (restart length)
-constexpr int kGmTotal = 200;     // Arnoldi steps per solve before giving up
+constexpr int kGmTotal = 40;      // Arnoldi steps per solve before giving up. A step costs one
+                                  // low-precision correction solve and one FP64 product with A;
+                                  // at n = 16384 the FP64 LU costs about 85 such steps and the
+                                  // low-precision LU already two thirds of the FP64 one, so a
+                                  // refinement much longer than one restart cycle cannot beat
+                                  // the FP64 solve and only adds to the fallback's cost
 constexpr double kGmTol = 1e-6;   // relative reduction of the preconditioned residual
-constexpr int kGmProbe = 12;      // after this many steps of a sweep, its rate so far must reach
+constexpr int kGmProbe = 12;      // from this many steps of a sweep on, its rate so far must reach
                                   // kGmTol within the solve's remaining Arnoldi budget, else
                                   // the solve is abandoned: M⁻¹A then has too many scattered
                                   // eigenvalues for a short Krylov space (kappa·u_f well above 1)
@@ -737,9 +742,9 @@ static void matvec(Ctx &c, long long n, long long nrhs, MixedWork &w, const doub
 
 // One GMRES-IR sweep: w.R holds r = b − A·x; X += d with d from GMRES on
 // M⁻¹A·d = M⁻¹r. Returns the Arnoldi steps taken (at most `budget`);
-// *hopeless is set (and X left alone) when, after kGmProbe steps, the
-// residual's average reduction per step would need more than `budget` steps
-// to reach kGmTol.
+// *hopeless is set (and X left alone) when, at any step from kGmProbe on, the
+// residual's average reduction per step so far would need more than `budget`
+// steps to reach kGmTol.
 static int gmres_sweep(Ctx &c, bool spd, char uplo, long long n, long long nrhs, MixedWork &w, GmWork &gw,
                        double *X, long long ldx, int budget, bool *hopeless) {
     *hopeless = false;
@@ -775,8 +780,10 @@ static int gmres_sweep(Ctx &c, bool spd, char uplo, long long n, long long nrhs,
         ++steps;
         const double ratio = fetch_scalar(c, gw.flag);
         if (ratio == 0.0) break;   // every column has finished
-        if (steps == kGmProbe) {
-            // steps needed at the rate so far: log(kGmTol) / (log(ratio) / steps)
+        if (steps >= kGmProbe) {
+            // steps needed at the rate so far: log(kGmTol) / (log(ratio) / steps); checked
+            // again after every later step, since a GMRES residual that slows down after a
+            // fast start would otherwise spend the whole budget before failing
             const bool slow = !(ratio < 1.0) || std::log(kGmTol) * steps / std::log(ratio) > (double)budget;
             if (slow) { *hopeless = true; return steps; }
         }

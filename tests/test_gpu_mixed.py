@@ -154,7 +154,7 @@ def test_gmres_ir_converges_where_plain_refinement_is_slow(orc):
     info, it, berr, x = _solve("general", a, b, "bf16")
     st = rl.mixed_last()
     assert info == 0 and it > 0, (it, st)
-    assert st["gmres_from"] >= 2 and st["gmres_sweeps"] >= 1 and 0 < st["gmres_steps"] <= 200
+    assert st["gmres_from"] >= 2 and st["gmres_sweeps"] >= 1 and 0 < st["gmres_steps"] <= 40
     _check_solution(orc, a, b, x, x0, 1e2, berr)
 
 
