@@ -9,11 +9,15 @@
 // the tiles of one triangle are launched and the diagonal tiles are masked.
 //
 // Design (gfx950):
-//  * 256 threads = 4 waves in a 2×2 arrangement; the workgroup tile is BM×BN
-//    (128×128 or 64×64), each wave owns (BM/2)×(BN/2) as a grid of 16×16
-//    matrix-core blocks; BK = 16 is staged through LDS, double-buffered, one
-//    barrier per K step. Operands are stored in LDS k-major ([k][m]) so that
-//    the 16 lanes of a matrix-core row group read 16 consecutive elements.
+//  * 128×128 tiles: 512 threads = 8 waves in a 4×2 arrangement, each wave
+//    owning 32×64 of the tile; 64×64 and 32×32 tiles: 256 threads = 4 waves
+//    in a 2×2 arrangement. Each wave's part is a grid of 16×16 matrix-core
+//    blocks; BK = 16 is staged through LDS, double-buffered, one barrier per
+//    K step. Operands are stored in LDS k-major ([k][m]) so that the 16 lanes
+//    of a matrix-core row group read 16 consecutive elements. (Four waves of
+//    64×64 on the 128-tile need 332 registers per lane, one wave per SIMD,
+//    and leave the matrix cores idle whenever that wave waits; eight waves of
+//    32×64 fit in 128, so a SIMD holds several.)
 //  * The K loop prefetches the next tile from HBM into registers while the
 //    matrix cores work on the current one.
 //  * XCD-aware launch: workgroup b runs on XCD b % 8; logical tiles are dealt
@@ -24,6 +28,8 @@
 //    the operand type in LDS (TL) may differ from the storage types, e.g. FP32
 //    factors multiplied in FP64 during iterative refinement.
 #include "common.hpp"
+
+#include <type_traits>
 
 namespace rl {
 
@@ -103,17 +109,22 @@ __device__ __forceinline__ void tri_band_tile(int tile, int T, int &t, int &u) {
     }
 }
 
+// Threads of a workgroup for a tile edge: 8 waves on 128-tiles, 4 otherwise.
+constexpr int k1_threads(int bm) { return bm == 128 ? 512 : 256; }
+
 template <typename TL, typename TA, typename TB, typename TC, bool TRA, bool TRB, int TRI, int BM,
           int BN, bool VEC>
-__global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
+__global__ __launch_bounds__(k1_threads(BM)) void gemm_k1(GemmArgs<TA, TB, TC> g) {
     constexpr int BK = 16;
+    constexpr int NT = k1_threads(BM);
+    constexpr int WM = NT / 128, WN = 2;   // waves along the tile's rows and columns
     // VEC: each thread moves pairs of elements that are adjacent in memory
     // (one 2-wide load per pair on full tiles; the host selects this only when
     // both operands' base and leading dimension keep every pair aligned); the
     // even pad keeps the pairs aligned in LDS as well.
     constexpr int PAD = VEC ? 2 : 1;
-    constexpr int MI = BM / 32, NI = BN / 32;
-    constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+    constexpr int MI = BM / WM / 16, NI = BN / WN / 16;
+    constexpr int EA = BM * BK / NT, EB = BN * BK / NT;
     typedef MfmaK1<TL> Op;
     typedef typename Op::acc_t acc_t;
 
@@ -156,7 +167,7 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
+    const int wm = (wave % WM) * (BM / WM), wn = (wave / WM) * (BN / WN);
 
     TA ra[EA];
     TB rb[EB];
@@ -166,29 +177,35 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
     auto a_coord = [&](int i, int &r, int &kk) {
         if (VEC) {
             const int p = i >> 1, h = i & 1;
-            if (!TRA) { r = 2 * (tid % (BM / 2)) + h; kk = tid / (BM / 2) + p * (512 / BM); }
-            else { kk = 2 * (tid % (BK / 2)) + h; r = tid / (BK / 2) + p * (512 / BK); }
+            if (!TRA) { r = 2 * (tid % (BM / 2)) + h; kk = tid / (BM / 2) + p * (2 * NT / BM); }
+            else { kk = 2 * (tid % (BK / 2)) + h; r = tid / (BK / 2) + p * (2 * NT / BK); }
         } else {
-            if (!TRA) { r = tid % BM; kk = tid / BM + i * (256 / BM); }
-            else { kk = tid % BK; r = tid / BK + i * (256 / BK); }
+            if (!TRA) { r = tid % BM; kk = tid / BM + i * (NT / BM); }
+            else { kk = tid % BK; r = tid / BK + i * (NT / BK); }
         }
     };
     auto b_coord = [&](int i, int &c, int &kk) {
         if (VEC) {
             const int p = i >> 1, h = i & 1;
-            if (TRB) { c = 2 * (tid % (BN / 2)) + h; kk = tid / (BN / 2) + p * (512 / BN); }
-            else { kk = 2 * (tid % (BK / 2)) + h; c = tid / (BK / 2) + p * (512 / BK); }
+            if (TRB) { c = 2 * (tid % (BN / 2)) + h; kk = tid / (BN / 2) + p * (2 * NT / BN); }
+            else { kk = 2 * (tid % (BK / 2)) + h; c = tid / (BK / 2) + p * (2 * NT / BK); }
         } else {
-            if (TRB) { c = tid % BN; kk = tid / BN + i * (256 / BN); }
-            else { kk = tid % BK; c = tid / BK + i * (256 / BK); }
+            if (TRB) { c = tid % BN; kk = tid / BN + i * (NT / BN); }
+            else { kk = tid % BK; c = tid / BK + i * (NT / BK); }
         }
     };
     typedef TA TA2 __attribute__((ext_vector_type(2)));
     typedef TB TB2 __attribute__((ext_vector_type(2)));
 
-    auto load_tiles = [&](long long k0) {
-        const bool afull = (m0 + BM <= M) && (k0 + BK <= K);
-        const bool bfull = (n0 + BN <= N) && (k0 + BK <= K);
+    // IN (compile time): the tile lies inside C and K is a multiple of BK, so
+    // no load needs a guard. Interior tiles run a copy of the K loop and of
+    // the epilogue without the edge checks (the checks inside the K loop cost
+    // the 128-tiles about a tenth of their rate); edge tiles take the guarded
+    // copy.
+    auto load_tiles = [&](long long k0, auto in_tag) {
+        constexpr bool IN = decltype(in_tag)::value;
+        const bool afull = IN || ((m0 + BM <= M) && (k0 + BK <= K));
+        const bool bfull = IN || ((n0 + BN <= N) && (k0 + BK <= K));
         if (afull && VEC) {
 #pragma unroll
             for (int i = 0; i < EA; i += 2) {
@@ -207,9 +224,9 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
                 const long long gr = m0 + r, gk = k0 + kk;
                 ra[i] = A[TRA ? gk + gr * g.lda : gr + gk * g.lda];
             }
-        } else {
-            // edge tile (rare in the large updates): guarded loads keep register
-            // pressure at the fast path's level
+        } else if (!IN) {
+            // edge tile: guarded loads keep register pressure at the fast
+            // path's level
 #pragma unroll
             for (int i = 0; i < EA; ++i) {
                 int r, kk;
@@ -236,7 +253,7 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
                 const long long gc = n0 + c, gk = k0 + kk;
                 rb[i] = B[TRB ? gc + gk * g.ldb : gk + gc * g.ldb];
             }
-        } else {
+        } else if (!IN) {
 #pragma unroll
             for (int i = 0; i < EB; ++i) {
                 int c, kk;
@@ -268,11 +285,6 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
         for (int j = 0; j < NI; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
     const long long KT = (K + BK - 1) / BK;
-    if (KT > 0) {
-        load_tiles(0);
-        store_tiles(0);
-        __syncthreads();
-    }
     // EARLY (paired loads on 128-tiles): the next K tile goes to LDS right
     // after the first quarter of the products (the other buffer was last read
     // before the previous barrier), and the waves raise their issue priority
@@ -283,46 +295,69 @@ __global__ __launch_bounds__(256) void gemm_k1(GemmArgs<TA, TB, TC> g) {
     // they take the paired loads alone (n = 1024 / 2048: 7 % faster).
     constexpr bool EARLY = VEC && BM == 128;
     constexpr int STORE_AFTER = EARLY ? 0 : BK / 4 - 1;
-    for (long long kt = 0; kt < KT; ++kt) {
-        const int buf = (int)(kt & 1);
-        if (kt + 1 < KT) load_tiles((kt + 1) * BK);
-        if (EARLY) __builtin_amdgcn_s_setprio(1);
-#pragma unroll
-        for (int ks = 0; ks < BK / 4; ++ks) {
-            const int kr = ks * 4 + (lane >> 4);
-            TL a[MI], b[NI];
-#pragma unroll
-            for (int i = 0; i < MI; ++i) a[i] = As[buf][kr][wm + i * 16 + (lane & 15)];
-#pragma unroll
-            for (int j = 0; j < NI; ++j) b[j] = Bs[buf][kr][wn + j * 16 + (lane & 15)];
-#pragma unroll
-            for (int i = 0; i < MI; ++i)
-#pragma unroll
-                for (int j = 0; j < NI; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
-            if (ks == STORE_AFTER && kt + 1 < KT) store_tiles(buf ^ 1);
+    auto k_loop = [&](auto in_tag) {
+        if (KT > 0) {
+            load_tiles(0, in_tag);
+            store_tiles(0);
+            __syncthreads();
         }
-        if (EARLY) __builtin_amdgcn_s_setprio(0);
-        __syncthreads();
-    }
+        for (long long kt = 0; kt < KT; ++kt) {
+            const int buf = (int)(kt & 1);
+            if (kt + 1 < KT) load_tiles((kt + 1) * BK, in_tag);
+            if (EARLY) __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+            for (int ks = 0; ks < BK / 4; ++ks) {
+                const int kr = ks * 4 + (lane >> 4);
+                TL a[MI], b[NI];
+#pragma unroll
+                for (int i = 0; i < MI; ++i) a[i] = As[buf][kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < NI; ++j) b[j] = Bs[buf][kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < MI; ++i)
+#pragma unroll
+                    for (int j = 0; j < NI; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
+                if (ks == STORE_AFTER && kt + 1 < KT) store_tiles(buf ^ 1);
+            }
+            if (EARLY) __builtin_amdgcn_s_setprio(0);
+            __syncthreads();
+        }
+    };
 
     const double alpha = g.alpha, beta = g.beta;
     TC *__restrict__ C = g.C;
+    // C := alpha·acc + beta·C on this wave's part (BZ: beta = 0, C not read)
+    auto epilogue = [&](auto in_tag, auto bz_tag) {
+        constexpr bool IN = decltype(in_tag)::value, BZ = decltype(bz_tag)::value;
 #pragma unroll
-    for (int i = 0; i < MI; ++i)
+        for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < NI; ++j)
+            for (int j = 0; j < NI; ++j)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const long long r = m0 + wm + i * 16 + Op::row(lane, v);
-                const long long cc = n0 + wn + j * 16 + (lane & 15);
-                if (r >= M || cc >= N) continue;
-                if (TRI == 1 && r < cc) continue;
-                if (TRI == 2 && r > cc) continue;
-                TC *p = C + r + cc * g.ldc;
-                const double val = (double)acc[i][j][v];
-                if (beta == 0.0) *p = (TC)(alpha * val);
-                else *p = (TC)(alpha * val + beta * (double)(*p));
-            }
+                for (int v = 0; v < 4; ++v) {
+                    const long long r = m0 + wm + i * 16 + Op::row(lane, v);
+                    const long long cc = n0 + wn + j * 16 + (lane & 15);
+                    if (!IN && (r >= M || cc >= N)) continue;
+                    if (TRI == 1 && r < cc) continue;
+                    if (TRI == 2 && r > cc) continue;
+                    TC *p = C + r + cc * g.ldc;
+                    const double val = (double)acc[i][j][v];
+                    if (BZ) *p = (TC)(alpha * val);
+                    else *p = (TC)(alpha * val + beta * (double)(*p));
+                }
+    };
+    typedef std::integral_constant<bool, true> yes;
+    typedef std::integral_constant<bool, false> no;
+    const bool inner = (m0 + BM <= M) && (n0 + BN <= N) && (K % BK == 0);
+    if (inner) k_loop(yes{});
+    else k_loop(no{});
+    if (inner) {
+        if (beta == 0.0) epilogue(yes{}, yes{});
+        else epilogue(yes{}, no{});
+    } else {
+        if (beta == 0.0) epilogue(no{}, yes{});
+        else epilogue(no{}, no{});
+    }
 }
 
 template <typename TL, typename TA, typename TB, typename TC, bool TRA, bool TRB, int TRI, int BM,
@@ -334,7 +369,7 @@ static void launch_k1(Ctx &c, const GemmArgs<TA, TB, TC> &args0, int ntiles = -1
     a.ntiles = ntiles >= 0 ? ntiles : (TRI ? a.tiles_m * (a.tiles_m + 1) / 2 : a.tiles_m * a.tiles_n);
     if (a.ntiles <= 0) return;
     const int grid = (a.ntiles + 7) / 8 * 8;
-    rl_launch(c, gemm_k1<TL, TA, TB, TC, TRA, TRB, TRI, BM, BM, VEC>, dim3(grid), dim3(256), 0, a);
+    rl_launch(c, gemm_k1<TL, TA, TB, TC, TRA, TRB, TRI, BM, BM, VEC>, dim3(grid), dim3(k1_threads(BM)), 0, a);
     RL_CHECK(hipGetLastError());
 }
 

@@ -77,7 +77,11 @@ template void potf2<float>(Ctx &, char, int, float *, long long, long long);
 // their best candidate and that row's window. Every 64-bit word of a record
 // carries the step's epoch in its upper half, so a reader polls exactly the
 // words it needs until their epochs match: no counter, no fence, no reset.
-// The winner is reduced identically in every workgroup, so all agree.
+// The winner is reduced identically in every workgroup, so all agree. Each
+// step updates the next column alone first, searches it and publishes the
+// next record, and only then updates the rest of the window, which thereby
+// runs while the record crosses the grid (the arithmetic per entry is the
+// same as updating the whole window at once).
 // ---------------------------------------------------------------------------
 struct PanelArgs {
     long long m, c0, lda;
@@ -165,6 +169,68 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
     // all loads in flight before any is used
     asm volatile("" ::: "memory");
 
+    // The workgroup's best candidate of one step, from the first live column's
+    // values v[k] of the two contents: thread, wave (the winning lane writes the
+    // candidate's window to LDS through put_window), then the workgroup (after
+    // one barrier, every thread reduces the four waves' results itself).
+    unsigned long long bk;
+    unsigned bp;
+    int bc, bwv;
+    auto cand_step = [&](PanelStep<T> &S2, const T *v, auto put_window) {
+        unsigned long long key = 0;
+        unsigned kp = 0xFFFFFFFFu;
+        int kc = -1, kb = 0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const unsigned long long kk = cand_key(fabs((double)v[k]), act[k]);
+            if (kk != 0 && cand_wins(kk, pos[k], key, kp)) { key = kk; kp = pos[k]; kc = cid[k]; kb = k; }
+        }
+        unsigned long long wk;
+        unsigned wp;
+        const int wl = wave_winner(key, kp, wk, wp);
+        const int wc = __builtin_amdgcn_readlane(kc, wl < 0 ? 0 : wl);
+        if (lane == wl && kb == 0) put_window(S2.cand[wave], 0);
+        if (lane == wl && kb == 1) put_window(S2.cand[wave], 1);
+        if (lane == 0) {
+            S2.rk[0][wave] = wk;
+            S2.rp[0][wave] = wp;
+            S2.rc[0][wave][0] = wl < 0 ? -1 : wc;
+            S2.rc[0][wave][1] = wave;
+        }
+        __syncthreads();
+        bk = S2.rk[0][0];
+        bp = S2.rp[0][0];
+        bc = S2.rc[0][0][0];
+        bwv = 0;
+#pragma unroll
+        for (int q = 1; q < 4; ++q)
+            if (cand_wins(S2.rk[0][q], S2.rp[0][q], bk, bp)) { bk = S2.rk[0][q]; bp = S2.rp[0][q]; bc = S2.rc[0][q][0]; bwv = q; }
+    };
+    // publish this workgroup's candidate of step jj: one word per thread
+    auto publish = [&](int jj, PanelStep<T> &S2) {
+        const unsigned long long ETj = (unsigned long long)(a.epoch + (unsigned)jj) << 32;
+        unsigned long long *mine = a.rec + ((size_t)jj * kRecSlots + g) * kRecWords;
+        if (tid < 4 + NC * W) {
+            unsigned v;
+            if (tid == 0) v = (unsigned)bk;
+            else if (tid == 1) v = (unsigned)(bk >> 32);
+            else if (tid == 2) v = bp;
+            else if (tid == 3) v = (unsigned)bc;
+            else v = Chunks<T>::get(S2.cand[bwv][(tid - 4) / NC], (tid - 4) % NC);
+            pubw(&mine[tid], ETj | v);
+        }
+    };
+
+    // step 0's candidate, as loaded
+    {
+        T v0[2] = {x[0][0], x[1][0]};
+        cand_step(ps[0], v0, [&](T *dst, int k) {
+#pragma unroll
+            for (int q = 0; q < W; ++q) dst[q] = k ? x[1][q] : x[0][q];
+        });
+        if (G > 1) publish(0, ps[0]);
+    }
+
     for (int j = 0; j < w; ++j) {
         PanelStep<T> &S = ps[j & 1];
         const unsigned d = (unsigned)(c0 + j);
@@ -172,55 +238,9 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
         const unsigned E = a.epoch + (unsigned)j;
         const unsigned long long ET = (unsigned long long)E << 32;
 
-        // -- best candidate: thread, wave (its window to LDS), workgroup
-        unsigned long long key = 0;
-        unsigned kp = 0xFFFFFFFFu;
-        int kc = -1, kb = 0;
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const unsigned long long kk = cand_key(fabs((double)x[k][0]), act[k]);
-            if (kk != 0 && cand_wins(kk, pos[k], key, kp)) { key = kk; kp = pos[k]; kc = cid[k]; kb = k; }
-        }
-        unsigned long long wk;
-        unsigned wp;
-        const int wl = wave_winner(key, kp, wk, wp);
-        const int wc = __builtin_amdgcn_readlane(kc, wl < 0 ? 0 : wl);
-        if (lane == wl && kb == 0) {
-#pragma unroll
-            for (int q = 0; q < W; ++q) S.cand[wave][q] = x[0][q];
-        }
-        if (lane == wl && kb == 1) {
-#pragma unroll
-            for (int q = 0; q < W; ++q) S.cand[wave][q] = x[1][q];
-        }
-        if (lane == 0) {
-            S.rk[0][wave] = wk;
-            S.rp[0][wave] = wp;
-            S.rc[0][wave][0] = wl < 0 ? -1 : wc;
-            S.rc[0][wave][1] = wave;
-        }
-        __syncthreads();
-        unsigned long long bk = S.rk[0][0];
-        unsigned bp = S.rp[0][0];
-        int bc = S.rc[0][0][0], bwv = 0;
-#pragma unroll
-        for (int q = 1; q < 4; ++q)
-            if (cand_wins(S.rk[0][q], S.rp[0][q], bk, bp)) { bk = S.rk[0][q]; bp = S.rp[0][q]; bc = S.rc[0][q][0]; bwv = q; }
-
         int src_g = -1;   // workgroup whose record holds the pivot row (G > 1)
         T spiv = T(0);    // the winner's first window entry, from the staged records
         if (G > 1) {
-            // publish this workgroup's candidate: one word per thread
-            unsigned long long *mine = a.rec + ((size_t)j * kRecSlots + g) * kRecWords;
-            if (tid < 4 + NC * W) {
-                unsigned v;
-                if (tid == 0) v = (unsigned)bk;
-                else if (tid == 1) v = (unsigned)(bk >> 32);
-                else if (tid == 2) v = bp;
-                else if (tid == 3) v = (unsigned)bc;
-                else v = Chunks<T>::get(S.cand[bwv][(tid - 4) / NC], (tid - 4) % NC);
-                pubw(&mine[tid], ET | v);
-            }
             if (G <= kPanelStageG) {
                 // every record whole in one round trip: the headers, one word per
                 // thread, and the windows, a wave per record and a lane per word
@@ -420,6 +440,22 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
                 pos[k] = d;
                 rstep[k] = j;
             }
+        }
+        // -- the next step's candidate first: its column is updated alone, the
+        // winning lane updates its whole window on the way to LDS, and the
+        // record goes out before the rest of the window is updated, so that
+        // update runs while the record crosses the grid
+        if (j + 1 < w) {
+            PanelStep<T> &S2 = ps[(j + 1) & 1];
+            T v1[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) v1[k] = x[k][1] - lk[k] * uc[0];
+            cand_step(S2, v1, [&](T *dst, int k) {
+#pragma unroll
+                for (int q = 0; q < W - 1; ++q) dst[q] = (k ? x[1][q + 1] - lk[1] * uc[q] : x[0][q + 1] - lk[0] * uc[q]);
+                dst[W - 1] = k ? x[1][W - 1] : x[0][W - 1];
+            });
+            if (G > 1) publish(j + 1, S2);
         }
         // x[q] <- x[q+1] - l·u[q+1] over the whole window: entries past the
         // live columns are never read, and a branch here would make the
