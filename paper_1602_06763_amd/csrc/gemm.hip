@@ -169,8 +169,15 @@ __global__ __launch_bounds__(k1_threads(BM)) void gemm_k1(GemmArgs<TA, TB, TC> g
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = (wave % WM) * (BM / WM), wn = (wave / WM) * (BN / WN);
 
-    TA ra[EA];
-    TB rb[EB];
+    // K tiles staged in registers on their way to LDS: one set on 128-tiles
+    // (stored a quarter step after its loads were issued), PF sets on the
+    // smaller tiles, whose short K steps cannot cover a global round trip
+    // with one tile in flight (a 64×64 tile's K step is about 1000 matrix-core
+    // cycles per wave; the round trip measured about twice that)
+    constexpr bool EARLY = VEC && BM == 128;
+    constexpr int PF = EARLY ? 1 : 4;
+    TA ra[PF][EA];
+    TB rb[PF][EB];
 
     // element coordinates of this thread's share of a K tile; with VEC,
     // elements 2p and 2p+1 are neighbours along the operand's contiguous index
@@ -202,7 +209,7 @@ __global__ __launch_bounds__(k1_threads(BM)) void gemm_k1(GemmArgs<TA, TB, TC> g
     // the epilogue without the edge checks (the checks inside the K loop cost
     // the 128-tiles about a tenth of their rate); edge tiles take the guarded
     // copy.
-    auto load_tiles = [&](long long k0, auto in_tag) {
+    auto load_tiles = [&](long long k0, auto in_tag, TA (&ra)[EA], TB (&rb)[EB]) {
         constexpr bool IN = decltype(in_tag)::value;
         const bool afull = IN || ((m0 + BM <= M) && (k0 + BK <= K));
         const bool bfull = IN || ((n0 + BN <= N) && (k0 + BK <= K));
@@ -263,7 +270,7 @@ __global__ __launch_bounds__(k1_threads(BM)) void gemm_k1(GemmArgs<TA, TB, TC> g
             }
         }
     };
-    auto store_tiles = [&](int buf) {
+    auto store_tiles = [&](int buf, const TA (&ra)[EA], const TB (&rb)[EB]) {
 #pragma unroll
         for (int i = 0; i < EA; ++i) {
             int r, kk;
@@ -293,34 +300,65 @@ __global__ __launch_bounds__(k1_threads(BM)) void gemm_k1(GemmArgs<TA, TB, TC> g
     // loads: from on par to 7 % faster, depending on the run. On 64-tiles
     // (four products per quarter and wave) it measured slower at n = 1024, so
     // they take the paired loads alone (n = 1024 / 2048: 7 % faster).
-    constexpr bool EARLY = VEC && BM == 128;
-    constexpr int STORE_AFTER = EARLY ? 0 : BK / 4 - 1;
-    auto k_loop = [&](auto in_tag) {
-        if (KT > 0) {
-            load_tiles(0, in_tag);
-            store_tiles(0);
-            __syncthreads();
+    // the products of one K tile from LDS buffer buf (after the first quarter
+    // of them, stage_next runs: the early store of the next tile)
+    auto k_step = [&](int buf, auto stage_next) {
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            TL a[MI], b[NI];
+#pragma unroll
+            for (int i = 0; i < MI; ++i) a[i] = As[buf][kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < NI; ++j) b[j] = Bs[buf][kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < MI; ++i)
+#pragma unroll
+                for (int j = 0; j < NI; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
+            if (ks == 0) stage_next();
         }
-        for (long long kt = 0; kt < KT; ++kt) {
-            const int buf = (int)(kt & 1);
-            if (kt + 1 < KT) load_tiles((kt + 1) * BK, in_tag);
-            if (EARLY) __builtin_amdgcn_s_setprio(1);
-#pragma unroll
-            for (int ks = 0; ks < BK / 4; ++ks) {
-                const int kr = ks * 4 + (lane >> 4);
-                TL a[MI], b[NI];
-#pragma unroll
-                for (int i = 0; i < MI; ++i) a[i] = As[buf][kr][wm + i * 16 + (lane & 15)];
-#pragma unroll
-                for (int j = 0; j < NI; ++j) b[j] = Bs[buf][kr][wn + j * 16 + (lane & 15)];
-#pragma unroll
-                for (int i = 0; i < MI; ++i)
-#pragma unroll
-                    for (int j = 0; j < NI; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
-                if (ks == STORE_AFTER && kt + 1 < KT) store_tiles(buf ^ 1);
+    };
+    auto k_loop = [&](auto in_tag) {
+        if (EARLY) {
+            if (KT > 0) {
+                load_tiles(0, in_tag, ra[0], rb[0]);
+                store_tiles(0, ra[0], rb[0]);
+                __syncthreads();
             }
-            if (EARLY) __builtin_amdgcn_s_setprio(0);
-            __syncthreads();
+            for (long long kt = 0; kt < KT; ++kt) {
+                const int buf = (int)(kt & 1);
+                if (kt + 1 < KT) load_tiles((kt + 1) * BK, in_tag, ra[0], rb[0]);
+                __builtin_amdgcn_s_setprio(1);
+                k_step(buf, [&] {
+                    if (kt + 1 < KT) store_tiles(buf ^ 1, ra[0], rb[0]);
+                });
+                __builtin_amdgcn_s_setprio(0);
+                __syncthreads();
+            }
+        } else {
+            // PF tiles in flight: step kt computes from LDS buffer kt & 1,
+            // moves tile kt + 1 (loaded PF - 1 steps earlier) into the other
+            // buffer and reuses tile kt's registers for tile kt + PF; the loop
+            // is unrolled by PF (even) so every register set index is static
+#pragma unroll
+            for (int p = 0; p < PF; ++p)
+                if (p < KT) load_tiles((long long)p * BK, in_tag, ra[p], rb[p]);
+            if (KT > 0) {
+                store_tiles(0, ra[0], rb[0]);
+                __syncthreads();
+            }
+            for (long long kt0 = 0; kt0 < KT; kt0 += PF) {
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    const long long kt = kt0 + u;
+                    if (kt < KT) {
+                        k_step(u & 1, [] {});
+                        if (kt + 1 < KT) store_tiles((u & 1) ^ 1, ra[(u + 1) % PF], rb[(u + 1) % PF]);
+                        if (kt + PF < KT) load_tiles((kt + PF) * BK, in_tag, ra[u], rb[u]);
+                        __syncthreads();
+                    }
+                }
+            }
         }
     };
 
