@@ -95,7 +95,11 @@ struct PanelArgs {
 
 constexpr int kPanelLds = kLuLeaf + 1;          // row stride of the finished-entry array
 constexpr unsigned int kPanelSpin = 1u << 22;   // poll bound per word group
-constexpr int kPanelStageG = 32;                // up to this many workgroups, records are read whole
+constexpr int kPanelStageG = 12;                // up to this many workgroups, records are read whole
+                                                // (one round trip); above, the headers and then
+                                                // the winner's row (two round trips but far fewer
+                                                // polled words: 3.73 against 3.94 us per column
+                                                // at 32 workgroups, even at 16, slower at 8)
 
 __device__ __forceinline__ void pubw(unsigned long long *p, unsigned long long v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
