@@ -170,12 +170,13 @@ __global__ __launch_bounds__(k1_threads(BM)) void gemm_k1(GemmArgs<TA, TB, TC> g
     const int wm = (wave % WM) * (BM / WM), wn = (wave / WM) * (BN / WN);
 
     // K tiles staged in registers on their way to LDS: one set on 128-tiles
-    // (stored a quarter step after its loads were issued), PF sets on the
-    // smaller tiles, whose short K steps cannot cover a global round trip
-    // with one tile in flight (a 64×64 tile's K step is about 1000 matrix-core
-    // cycles per wave; the round trip measured about twice that)
+    // (stored a quarter step after its loads were issued when they are paired,
+    // after the whole step otherwise; more sets cost the 128-tiles their
+    // second workgroup per CU), PF sets on the smaller tiles, whose short K
+    // steps cannot cover a global round trip with one tile in flight (a 64×64
+    // tile's K step is about 1000 matrix-core cycles per wave)
     constexpr bool EARLY = VEC && BM == 128;
-    constexpr int PF = EARLY ? 1 : 4;
+    constexpr int PF = BM == 128 ? 1 : 4;
     TA ra[PF][EA];
     TB rb[PF][EB];
 
@@ -300,8 +301,10 @@ __global__ __launch_bounds__(k1_threads(BM)) void gemm_k1(GemmArgs<TA, TB, TC> g
     // loads: from on par to 7 % faster, depending on the run. On 64-tiles
     // (four products per quarter and wave) it measured slower at n = 1024, so
     // they take the paired loads alone (n = 1024 / 2048: 7 % faster).
-    // the products of one K tile from LDS buffer buf (after the first quarter
-    // of them, stage_next runs: the early store of the next tile)
+    // the products of one K tile from LDS buffer buf; stage_next runs after
+    // the first quarter of them on paired 128-tiles (the early store of the
+    // next tile) and after the last quarter otherwise
+    constexpr int STORE_AFTER = EARLY ? 0 : BK / 4 - 1;
     auto k_step = [&](int buf, auto stage_next) {
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
@@ -315,11 +318,11 @@ __global__ __launch_bounds__(k1_threads(BM)) void gemm_k1(GemmArgs<TA, TB, TC> g
             for (int i = 0; i < MI; ++i)
 #pragma unroll
                 for (int j = 0; j < NI; ++j) acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
-            if (ks == 0) stage_next();
+            if (ks == STORE_AFTER) stage_next();
         }
     };
     auto k_loop = [&](auto in_tag) {
-        if (EARLY) {
+        if (PF == 1) {
             if (KT > 0) {
                 load_tiles(0, in_tag, ra[0], rb[0]);
                 store_tiles(0, ra[0], rb[0]);
@@ -328,11 +331,11 @@ __global__ __launch_bounds__(k1_threads(BM)) void gemm_k1(GemmArgs<TA, TB, TC> g
             for (long long kt = 0; kt < KT; ++kt) {
                 const int buf = (int)(kt & 1);
                 if (kt + 1 < KT) load_tiles((kt + 1) * BK, in_tag, ra[0], rb[0]);
-                __builtin_amdgcn_s_setprio(1);
+                if (EARLY) __builtin_amdgcn_s_setprio(1);
                 k_step(buf, [&] {
                     if (kt + 1 < KT) store_tiles(buf ^ 1, ra[0], rb[0]);
                 });
-                __builtin_amdgcn_s_setprio(0);
+                if (EARLY) __builtin_amdgcn_s_setprio(0);
                 __syncthreads();
             }
         } else {
@@ -352,7 +355,7 @@ __global__ __launch_bounds__(k1_threads(BM)) void gemm_k1(GemmArgs<TA, TB, TC> g
                 for (int u = 0; u < PF; ++u) {
                     const long long kt = kt0 + u;
                     if (kt < KT) {
-                        k_step(u & 1, [] {});
+                        k_step(u & 1, [] {});   // (PF > 1: stores below)
                         if (kt + 1 < KT) store_tiles((u & 1) ^ 1, ra[(u + 1) % PF], rb[(u + 1) % PF]);
                         if (kt + PF < KT) load_tiles((kt + PF) * BK, in_tag, ra[u], rb[u]);
                         __syncthreads();
