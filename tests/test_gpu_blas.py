@@ -14,7 +14,8 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("ta", ["N", "T"])
 @pytest.mark.parametrize("tb", ["N", "T"])
-@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (65, 33, 17), (130, 257, 300), (1000, 600, 129), (64, 64, 0)])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (65, 33, 17), (130, 257, 300), (1000, 600, 129), (1000, 600, 208),
+                                   (64, 64, 0)])
 def test_gemm(ta, tb, m, n, k):
     a = gen.general_uniform(m if ta == "N" else k, k if ta == "N" else m, seed=1)
     b = gen.general_uniform(k if tb == "N" else n, n if tb == "N" else k, seed=2)
@@ -45,11 +46,14 @@ def _dev_layout(a, layout):
 @pytest.mark.parametrize("ta", ["N", "T"])
 @pytest.mark.parametrize("tb", ["N", "T"])
 @pytest.mark.parametrize("layout", ["pairs", "odd_ld", "odd_base"])
-def test_gemm_large_tiles(ta, tb, layout):
-    """Sizes that take the 128x128 tiles (at least two per CU), ragged in every
-    dimension, with operands whose adjacent elements pair up and with operands
-    that force element-wise loads."""
-    m, n, k = 2900, 2836, 37
+@pytest.mark.parametrize("k", [37, 160])
+def test_gemm_large_tiles(ta, tb, layout, k):
+    """Sizes that take the 128x128 tiles (at least two per CU), ragged in M and
+    N, with operands whose adjacent elements pair up and with operands that
+    force element-wise loads; K = 160 (a multiple of the K step) sends the
+    interior tiles down the unguarded path and the edge tiles down the
+    guarded one."""
+    m, n = 2900, 2836
     a = gen.general_uniform(m if ta == "N" else k, k if ta == "N" else m, seed=11)
     b = gen.general_uniform(k if tb == "N" else n, n if tb == "N" else k, seed=12)
     c = gen.general_uniform(m, n, seed=13)
@@ -63,10 +67,12 @@ def test_gemm_large_tiles(ta, tb, layout):
 @pytest.mark.parametrize("uplo", ["L", "U"])
 @pytest.mark.parametrize("trans", ["N", "T"])
 @pytest.mark.parametrize("layout", ["pairs", "odd_ld"])
-def test_syrk_large_tiles(uplo, trans, layout):
+@pytest.mark.parametrize("k", [20, 48])
+def test_syrk_large_tiles(uplo, trans, layout, k):
     """A triangular update on 128x128 tiles whose last, partly filled round runs
-    as 64x64 quarters (n = 4100: 561 tiles for 512 slots)."""
-    n, k = 4100, 20
+    as 64x64 quarters (n = 4100: 561 tiles for 512 slots); K = 48 takes the
+    unguarded path on the interior tiles."""
+    n = 4100
     a = gen.general_uniform(n if trans == "N" else k, k if trans == "N" else n, seed=14)
     c = gen.general_uniform(n, n, seed=15)
     A, lda = _dev_layout(a, layout)
