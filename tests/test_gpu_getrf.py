@@ -120,10 +120,12 @@ def test_getrs(orc, trans, nrhs):
     assert orc.backward_error(g if trans == "N" else g.T, to_host(bt), b2)[0] <= 10 * n * U64
 
 
-@pytest.mark.parametrize("m,n", [(20000, 64), (40000, 40)])
+@pytest.mark.parametrize("m,n", [(5500, 64), (6400, 48), (20000, 64), (40000, 40)])
 def test_tall_panels_many_workgroups(orc, m, n):
-    """Tall panels spread over 40 and 79 cooperating workgroups (records staged in
-    LDS, and read straight from memory beyond 64 workgroups)."""
+    """Tall panels spread over 11, 13, 40 and 79 cooperating workgroups: up to 12
+    workgroups every record is read whole in one round trip (11 uses the third
+    window load of each thread), from 13 on the headers and then the pivot
+    row."""
     a = gen.general_uniform(m, n, seed=m + n)
     f, piv, info = _run(a)
     ref, rpiv, rinfo = orc.getrf(a)
