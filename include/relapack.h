@@ -214,8 +214,11 @@ void relapack_cpotrf(char uplo, int n, void *A, int lda, int *info);
  * relapack_dgetrf. A: m×n complex (z: pairs of doubles, c: pairs of floats),
  * column-major. info = k > 0: U(k, k) is exactly zero (both parts), the first
  * such k; the factorization completes. Leaves are panels of at most 16
- * columns factored by one workgroup (rows below the diagonal in global
- * memory), their interchanges applied at once to every other column.
+ * columns, factored as relapack_dgetrf's (ceil(rows / 512) cooperating
+ * workgroups with bounded waits: info <= -2000 if other GPU work keeps some
+ * from starting for about a second), or, where the chip cannot hold that
+ * grid at once, by one workgroup (no limit on m); their interchanges are
+ * applied at once to every other column.
  * Errors: m -1, n -2, lda -4.
  */
 void relapack_zgetrf(int m, int n, void *A, int lda, int *ipiv, int *info);

@@ -11,6 +11,8 @@
 #include <cstdint>
 #include <vector>
 
+#include "cx.hpp"
+
 namespace rl {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -201,6 +203,11 @@ void trsm_leaf(Ctx &c, bool lower_eff, bool unit, int t, const TT *T, long long 
                long long nvec, TB *B, long long se, long long sr);
 template <typename T>
 void getf2_panel(Ctx &c, long long m, int w, T *A, long long lda, long long off, int *ipiv);
+// The same cooperative panel for the complex instances (T = cx<double> or
+// cx<float>, at most kZLuLeaf columns); returns false, launching nothing,
+// when the chip cannot hold all its workgroups at once.
+template <typename T>
+bool getf2_panel_cx(Ctx &c, long long m, int w, T *A, long long lda, long long off, int *ipiv);
 template <typename T>
 void laswp_leaf(Ctx &c, T *A, long long lda, long long k0, int w, long long m, const int *ipiv, long long blk0,
                 long long blk1);

@@ -24,36 +24,7 @@
 
 namespace rl {
 
-template <typename R>
-struct alignas(2 * sizeof(R)) cx {
-    R re, im;
-};
-
-template <typename R>
-__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
-    return cx<R>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-template <typename R>
-__device__ __forceinline__ cx<R> cconj(cx<R> a) {
-    return cx<R>{a.re, -a.im};
-}
-template <typename R>
-__device__ __forceinline__ cx<R> csub(cx<R> a, cx<R> b) {
-    return cx<R>{a.re - b.re, a.im - b.im};
-}
-template <typename R>
-__device__ __forceinline__ cx<R> cdiv(cx<R> a, cx<R> p) {
-    const R den = p.re * p.re + p.im * p.im;
-    const cx<R> q = cmul(a, cconj(p));
-    return cx<R>{q.re / den, q.im / den};
-}
-template <typename R>
-__device__ __forceinline__ R cabs1(cx<R> z) {
-    return fabs(z.re) + fabs(z.im);
-}
-
 constexpr int kZLeaf = 64;     // Cholesky and triangular-solve leaves
-constexpr int kZLuLeaf = 16;   // LU panel width
 
 // ---------------------------------------------------------------------------
 // C := beta·C + alpha·op(A)·op(B) on the matrix cores, alpha and beta real;
@@ -539,10 +510,14 @@ static void zgetrf_rec(Ctx &c, long long m, long long ncols, cx<R> *A, long long
                        long long w) {
     if (w <= kZLuLeaf) {
         if (plan_record(c, PK_ZLEAF, m - c0, w, w)) return;
-        trace_kernel_begin(c);
-        rl_launch(c, zgetf2_k<R>, dim3(1), dim3(1024), 0, m, (int)w, A, lda, c0, ipiv, c.dstat);
-        RL_CHECK(hipGetLastError());
-        trace_kernel_end(c, PK_ZLEAF, 8.0 * (m - c0) * w * w / 2.0, 32.0 * (m - c0) * w);
+        // the cooperative panel (row blocks across the CUs); one workgroup
+        // when the chip cannot hold its grid
+        if (!getf2_panel_cx<cx<R>>(c, m, (int)w, A, lda, c0, ipiv)) {
+            trace_kernel_begin(c);
+            rl_launch(c, zgetf2_k<R>, dim3(1), dim3(1024), 0, m, (int)w, A, lda, c0, ipiv, c.dstat);
+            RL_CHECK(hipGetLastError());
+            trace_kernel_end(c, PK_ZLEAF, 8.0 * (m - c0) * w * w / 2.0, 32.0 * (m - c0) * w);
+        }
         if (ncols > w)
             hipLaunchKernelGGL(zlaswp_k<R>, dim3((unsigned)((ncols - w + 255) / 256)), dim3(256), 0, c.stream, ncols, c0,
                                (int)w, A, lda, (const int *)ipiv, c0, c0 + w);

@@ -50,9 +50,10 @@ template void potf2<float>(Ctx &, char, int, float *, long long, long long);
 
 // ---------------------------------------------------------------------------
 // getf2 panel: partial-pivoting LU of the m_p × w panel A[c0:m, c0:c0+w]
-// (w <= 32) with dgetf2's semantics (Sec. 5 keeps LAPACK's statement of the
-// problem): for column j, with d = c0 + j,
-//   - the pivot p is the first position i >= d with the largest |a_ij| (a NaN
+// (w <= 32; 16 for the complex types) with dgetf2's semantics (Sec. 5 keeps
+// LAPACK's statement of the problem): for column j, with d = c0 + j,
+//   - the pivot p is the first position i >= d with the largest |a_ij|
+//     (|re| + |im| for complex entries, as izamax picks) (a NaN
 //     never wins; with no candidate at all, p = d); ipiv[d] = p + 1;
 //   - if a_pj != 0 (NaN counts as nonzero) rows d and p are interchanged and
 //     the column below the diagonal is divided by the pivot; otherwise info
@@ -93,7 +94,6 @@ struct PanelArgs {
     unsigned int epoch;        // step j publishes with epoch + j
 };
 
-constexpr int kPanelLds = kLuLeaf + 1;          // row stride of the finished-entry array
 constexpr unsigned int kPanelSpin = 1u << 22;   // poll bound per word group
 constexpr int kPanelStageG = 12;                // up to this many workgroups, records are read whole
                                                 // (one round trip); above, the headers and then
@@ -108,24 +108,53 @@ __device__ __forceinline__ unsigned long long subw(const unsigned long long *p) 
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// 32-bit chunks of a value, for epoch-tagged words
-template <typename T> struct Chunks;
-template <> struct Chunks<double> {
-    static constexpr int N = 2;
+// Scalar traits of the panel: window width W, the value's 32-bit chunks for
+// the epoch-tagged words (NC of them), the pivot magnitude, the quotient and
+// the update x - l·u, zero, and a broadcast from one lane. The complex
+// instances (the c/z types) take 16 columns (their window then holds as many
+// registers as the real one) and the magnitude |re| + |im|.
+template <typename T> struct PanelT;
+template <> struct PanelT<double> {
+    static constexpr int W = kLuLeaf, NC = 2;
     static __device__ __forceinline__ unsigned get(double v, int h) {
         return h ? (unsigned)__double2hiint(v) : (unsigned)__double2loint(v);
     }
+    static __device__ __forceinline__ double mag(double v) { return fabs(v); }
+    static __device__ __forceinline__ double div(double a, double p) { return a / p; }
+    static __device__ __forceinline__ double fms(double x, double l, double u) { return x - l * u; }
+    static __device__ __forceinline__ double zero() { return 0.0; }
+    static __device__ __forceinline__ double bcast(double v, int l) { return lane_bcast(v, l); }
 };
-template <> struct Chunks<float> {
-    static constexpr int N = 1;
+template <> struct PanelT<float> {
+    static constexpr int W = kLuLeaf, NC = 1;
     static __device__ __forceinline__ unsigned get(float v, int) { return __float_as_uint(v); }
+    static __device__ __forceinline__ double mag(float v) { return fabs((double)v); }
+    static __device__ __forceinline__ float div(float a, float p) { return a / p; }
+    static __device__ __forceinline__ float fms(float x, float l, float u) { return x - l * u; }
+    static __device__ __forceinline__ float zero() { return 0.f; }
+    static __device__ __forceinline__ float bcast(float v, int l) { return lane_bcast(v, l); }
+};
+template <typename R> struct PanelT<cx<R>> {
+    static constexpr int W = kZLuLeaf, NC = 2 * PanelT<R>::NC;
+    static __device__ __forceinline__ unsigned get(cx<R> v, int h) {
+        return h < PanelT<R>::NC ? PanelT<R>::get(v.re, h) : PanelT<R>::get(v.im, h - PanelT<R>::NC);
+    }
+    // |re| + |im| in the working precision, as the oracle and the one-workgroup
+    // complex panel decide it
+    static __device__ __forceinline__ double mag(cx<R> v) { return (double)cabs1(v); }
+    static __device__ __forceinline__ cx<R> div(cx<R> a, cx<R> p) { return cdiv(a, p); }
+    static __device__ __forceinline__ cx<R> fms(cx<R> x, cx<R> l, cx<R> u) { return csub(x, cmul(l, u)); }
+    static __device__ __forceinline__ cx<R> zero() { return cx<R>{R(0), R(0)}; }
+    static __device__ __forceinline__ cx<R> bcast(cx<R> v, int l) {
+        return cx<R>{lane_bcast(v.re, l), lane_bcast(v.im, l)};
+    }
 };
 
 // Per-step LDS of the panel, double buffered by step parity: a wave that has
 // moved on to the next step never overwrites what a slower wave still reads.
 template <typename T>
 struct PanelStep {
-    T cand[4][kLuLeaf];            // window of each wave's best candidate
+    T cand[4][PanelT<T>::W];       // window of each wave's best candidate
     unsigned long long rk[2][4];   // [workgroup / grid reduction][wave]
     unsigned rp[2][4];
     int rc[2][4][2];
@@ -133,11 +162,13 @@ struct PanelStep {
 
 template <typename T>
 __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArgs a) {
-    constexpr int W = kLuLeaf;
+    typedef PanelT<T> P;
+    constexpr int W = P::W;
     constexpr int R = kPanelRows;
-    constexpr int NC = Chunks<T>::N;
+    constexpr int NC = P::NC;
+    constexpr int LDSW = W + 1;                // row stride of the finished-entry array
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    T *F = reinterpret_cast<T *>(smem_raw);   // multipliers [R][kPanelLds]
+    T *F = reinterpret_cast<T *>(smem_raw);   // multipliers [R][LDSW]
     __shared__ PanelStep<T> ps[2];
     __shared__ T Urow[W][W + 1];               // row j of U, from the step that retired it
     __shared__ T dwin[W];                      // row d's window when it drives the update
@@ -186,7 +217,7 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
         int kc = -1, kb = 0;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            const unsigned long long kk = cand_key(fabs((double)v[k]), act[k]);
+            const unsigned long long kk = cand_key(P::mag(v[k]), act[k]);
             if (kk != 0 && cand_wins(kk, pos[k], key, kp)) { key = kk; kp = pos[k]; kc = cid[k]; kb = k; }
         }
         unsigned long long wk;
@@ -220,7 +251,7 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
             else if (tid == 1) v = (unsigned)(bk >> 32);
             else if (tid == 2) v = bp;
             else if (tid == 3) v = (unsigned)bc;
-            else v = Chunks<T>::get(S2.cand[bwv][(tid - 4) / NC], (tid - 4) % NC);
+            else v = P::get(S2.cand[bwv][(tid - 4) / NC], (tid - 4) % NC);
             pubw(&mine[tid], ETj | v);
         }
     };
@@ -243,7 +274,7 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
         const unsigned long long ET = (unsigned long long)E << 32;
 
         int src_g = -1;   // workgroup whose record holds the pivot row (G > 1)
-        T spiv = T(0);    // the winner's first window entry, from the staged records
+        T spiv = P::zero();   // the winner's first window entry, from the staged records
         if (G > 1) {
             if (G <= kPanelStageG) {
                 // every record whole in one round trip: the headers, one word per
@@ -297,7 +328,7 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
                 unsigned long long tk = 0;
                 unsigned tp = 0xFFFFFFFFu;
                 int tc = -1;
-                T w0 = T(0);
+                T w0 = P::zero();
                 if (lane < G) {
                     const unsigned *h = &stage[lane * kRecWords];
                     tk = ((unsigned long long)h[1] << 32) | h[0];
@@ -311,7 +342,7 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
                 bk = gk2;
                 bp = gp2;
                 bc = __builtin_amdgcn_readlane(tc, gl < 0 ? 0 : gl);
-                spiv = lane_bcast(w0, gl < 0 ? 0 : gl);
+                spiv = P::bcast(w0, gl < 0 ? 0 : gl);
                 src_g = gl;
             } else {
             // every workgroup's header, one per thread
@@ -392,7 +423,7 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
 #pragma unroll
                         for (int q = 0; q < W; ++q)
 #pragma unroll
-                            for (int h = 0; h < NC; ++h) pubw(&srcrec[4 + NC * q + h], ET | Chunks<T>::get(x[k][q], h));
+                            for (int h = 0; h < NC; ++h) pubw(&srcrec[4 + NC * q + h], ET | P::get(x[k][q], h));
                     }
                 }
             }
@@ -431,11 +462,11 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
             const int r = tid + 256 * k;
             const bool ret = act[k] && (useD ? pos[k] == d : cid[k] == bc);
             const bool sc = act[k] && !ret;
-            const T l = nz ? x[k][0] / piv : x[k][0];
-            lk[k] = sc ? l : T(0);
+            const T l = nz ? P::div(x[k][0], piv) : x[k][0];
+            lk[k] = sc ? l : P::zero();
             if (sc) {
                 if (!useD && pos[k] == d) pos[k] = p;
-                F[r * kPanelLds + j] = l;
+                F[r * LDSW + j] = l;
             }
             if (ret) {
 #pragma unroll
@@ -453,10 +484,10 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
             PanelStep<T> &S2 = ps[(j + 1) & 1];
             T v1[2];
 #pragma unroll
-            for (int k = 0; k < 2; ++k) v1[k] = x[k][1] - lk[k] * uc[0];
+            for (int k = 0; k < 2; ++k) v1[k] = P::fms(x[k][1], lk[k], uc[0]);
             cand_step(S2, v1, [&](T *dst, int k) {
 #pragma unroll
-                for (int q = 0; q < W - 1; ++q) dst[q] = (k ? x[1][q + 1] - lk[1] * uc[q] : x[0][q + 1] - lk[0] * uc[q]);
+                for (int q = 0; q < W - 1; ++q) dst[q] = (k ? P::fms(x[1][q + 1], lk[1], uc[q]) : P::fms(x[0][q + 1], lk[0], uc[q]));
                 dst[W - 1] = k ? x[1][W - 1] : x[0][W - 1];
             });
             if (G > 1) publish(j + 1, S2);
@@ -467,7 +498,7 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
 #pragma unroll
         for (int k = 0; k < 2; ++k)
 #pragma unroll
-            for (int q = 0; q < W - 1; ++q) x[k][q] = x[k][q + 1] - lk[k] * uc[q];
+            for (int q = 0; q < W - 1; ++q) x[k][q] = P::fms(x[k][q + 1], lk[k], uc[q]);
     }
     __syncthreads();
     if (g == 0) {
@@ -482,31 +513,28 @@ __global__ __launch_bounds__(256) void getf2_panel_k(T *__restrict__ A, PanelArg
             const long long fp = (long long)pos[k];
             const int rs = rstep[k] < 0 ? W : rstep[k];
             for (int q = 0; q < w; ++q) {
-                const T lv = F[r * kPanelLds + q];
+                const T lv = F[r * LDSW + q];
                 const T uv = Urow[min(rs, W - 1)][max(q - rs, 0)];
                 A[fp + (c0 + q) * a.lda] = q < rs ? lv : uv;
             }
-            a.rowsrc[fp] = cid[k];
+            if (a.rowsrc) a.rowsrc[fp] = cid[k];
         }
     }
 }
 
+// Launch of the cooperative panel. Every workgroup waits on every other one,
+// so all G must be resident: with strict, a launch the chip cannot hold is an
+// error; otherwise nothing is launched and false returned.
 template <typename T>
-void getf2_panel(Ctx &c, long long m, int w, T *A, long long lda, long long c0, int *ipiv) {
-    if (plan_record(c, PK_GETF2, m - c0, w, w)) return;
+static bool panel_launch(Ctx &c, long long m, int w, T *A, long long lda, long long c0, int *ipiv, int *rowsrc,
+                         int kind, double flops, bool strict) {
     const long long mp = m - c0;
-    if (mp <= 0 || w <= 0) return;
     const int G = (int)((mp + kPanelRows - 1) / kPanelRows);
-    // every workgroup waits on every other one: all of them must be resident
-    if (G > c.num_cu || G > kPanelMaxWG) { launch_error(hipErrorInvalidConfiguration); return; }
-    PanelArgs a{};
-    a.m = m; a.c0 = c0; a.lda = lda; a.w = w; a.G = G;
-    a.ipiv = ipiv;
-    a.rowsrc = c.rowsrc;
-    a.st = c.dstat;
-    a.rec = panel_records(c, &a.epoch);
-    if (!a.rec) return;
-    const size_t shm = (size_t)kPanelRows * kPanelLds * sizeof(T);
+    if (G > c.num_cu || G > kPanelMaxWG) {
+        if (strict) launch_error(hipErrorInvalidConfiguration);
+        return false;
+    }
+    const size_t shm = (size_t)kPanelRows * (PanelT<T>::W + 1) * sizeof(T);
     static size_t attr_bytes = 0;
     static int per_cu = -1;   // workgroups of this kernel one CU can hold
     if (shm > attr_bytes) {
@@ -520,17 +548,46 @@ void getf2_panel(Ctx &c, long long m, int w, T *A, long long lda, long long c0, 
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, getf2_panel_k<T>, 256, shm) != hipSuccess) nb = 0;
         per_cu = nb;
     }
-    // the workgroups wait on each other: refuse a launch the chip cannot hold
-    // at once instead of letting the bounded waits expire
-    if ((long long)per_cu * c.num_cu < G) { launch_error(hipErrorCooperativeLaunchTooLarge); return; }
+    // refuse a launch the chip cannot hold at once instead of letting the
+    // bounded waits expire
+    if ((long long)per_cu * c.num_cu < G) {
+        if (strict) launch_error(hipErrorCooperativeLaunchTooLarge);
+        return false;
+    }
+    PanelArgs a{};
+    a.m = m; a.c0 = c0; a.lda = lda; a.w = w; a.G = G;
+    a.ipiv = ipiv;
+    a.rowsrc = rowsrc;
+    a.st = c.dstat;
+    a.rec = panel_records(c, &a.epoch);
+    if (!a.rec) return strict;
     trace_kernel_begin(c);
     rl_launch(c, getf2_panel_k<T>, dim3(G), dim3(256), (unsigned)shm, A, a);
     RL_CHECK(hipGetLastError());
-    trace_kernel_end(c, PK_GETF2, (double)mp * w * w, 2.0 * sizeof(T) * mp * w);
+    trace_kernel_end(c, kind, flops, 2.0 * sizeof(T) * mp * w);
+    return true;
+}
+
+template <typename T>
+void getf2_panel(Ctx &c, long long m, int w, T *A, long long lda, long long c0, int *ipiv) {
+    if (plan_record(c, PK_GETF2, m - c0, w, w)) return;
+    if (m - c0 <= 0 || w <= 0) return;
+    panel_launch<T>(c, m, w, A, lda, c0, ipiv, c.rowsrc, PK_GETF2, (double)(m - c0) * w * w, true);
 }
 
 template void getf2_panel<double>(Ctx &, long long, int, double *, long long, long long, int *);
 template void getf2_panel<float>(Ctx &, long long, int, float *, long long, long long, int *);
+
+template <typename T>
+bool getf2_panel_cx(Ctx &c, long long m, int w, T *A, long long lda, long long c0, int *ipiv) {
+    if (m - c0 <= 0 || w <= 0) return true;
+    // the complex recursion applies the interchanges to the other columns
+    // from ipiv itself (no source-row list)
+    return panel_launch<T>(c, m, w, A, lda, c0, ipiv, nullptr, PK_ZLEAF, 4.0 * (m - c0) * w * w, false);
+}
+
+template bool getf2_panel_cx<cx<double>>(Ctx &, long long, int, cx<double> *, long long, long long, int *);
+template bool getf2_panel_cx<cx<float>>(Ctx &, long long, int, cx<float> *, long long, long long, int *);
 
 // ---------------------------------------------------------------------------
 // laswp after a panel: the panel's w interchanges, applied to the columns of

@@ -120,6 +120,39 @@ def test_zgetrf_exact_and_pivot_rule(orc, n):
     assert rl.zgetrf(d, piv) == 0 and piv.cpu().numpy()[0] == 2
 
 
+@pytest.mark.parametrize("m,n", [(1600, 40), (5500, 16), (7000, 24), (13000, 33)])
+def test_zgetrf_tall_panels(orc, m, n):
+    """Tall panels spread their rows over several cooperating workgroups of
+    512 rows (4, 11, 14 and 26 of them: records read whole up to 12, headers
+    then the winner's row above), with a ragged last workgroup."""
+    _setup()
+    import torch
+
+    a = gen.general_complex(m, n, seed=m + n)
+    d = _dev(a, ld=m + 3)
+    piv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    assert rl.zgetrf(d, piv) == 0
+    ref, rpiv, info = orc.zgetrf(a)
+    assert info == 0
+    assert np.array_equal(piv.cpu().numpy(), rpiv)
+    assert rel_fro(_host(d), ref) <= 1e-10
+
+
+def test_zgetrf_tall_zero_pivot(orc):
+    _setup()
+    import torch
+
+    a = gen.general_complex(3000, 48, seed=11)
+    a[:, 20] = 0.0
+    d = _dev(a)
+    piv = torch.zeros(48, dtype=torch.int32, device="cuda")
+    info = rl.zgetrf(d, piv)
+    ref, rpiv, rinfo = orc.zgetrf(a)
+    assert info == rinfo == 21
+    assert np.array_equal(piv.cpu().numpy(), rpiv)
+    assert rel_fro(_host(d), ref) <= 1e-10
+
+
 def test_zgetrf_zero_pivot_completes(orc):
     _setup()
     import torch
@@ -154,5 +187,16 @@ def test_single_precision_complex(orc):
     up = np.triu(f)
     import oracle
 
+    pa = oracle.apply_ipiv(g, piv.cpu().numpy())
+    assert np.linalg.norm(pa - lo @ up) / np.linalg.norm(g) <= 20 * n * U32
+    # a tall single-precision panel over 12 cooperating workgroups
+    m, n = 6000, 20
+    g = gen.general_complex(m, n, seed=6).astype(np.complex64).astype(np.complex128)
+    d = _dev(g, single=True)
+    piv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    assert rl.zgetrf(d, piv) == 0
+    f = _host(d)
+    lo = np.tril(f, -1)[:, :n] + np.eye(m, n)
+    up = np.triu(f[:n])
     pa = oracle.apply_ipiv(g, piv.cpu().numpy())
     assert np.linalg.norm(pa - lo @ up) / np.linalg.norm(g) <= 20 * n * U32
