@@ -490,6 +490,7 @@ static void zgetrf_call(int m, int n, void *A, int lda, int *ipiv, int *info) {
     if (m == 0 || n == 0) return;
     Ctx &c = ctx();
     if (!call_begin(c, false)) { *info = call_end(c); return; }
+    ensure_rowsrc(c, (size_t)m);
     zgetrf_top<R>(c, m, n, A, lda, ipiv);
     *info = call_end(c);
 }

@@ -204,8 +204,9 @@ void trsm_leaf(Ctx &c, bool lower_eff, bool unit, int t, const TT *T, long long 
 template <typename T>
 void getf2_panel(Ctx &c, long long m, int w, T *A, long long lda, long long off, int *ipiv);
 // The same cooperative panel for the complex instances (T = cx<double> or
-// cx<float>, at most kZLuLeaf columns); returns false, launching nothing,
-// when the chip cannot hold all its workgroups at once.
+// cx<float>, at most kZLuLeaf columns), the source row of every position
+// into c.rowsrc; returns false, launching nothing, when the chip cannot hold
+// all its workgroups at once or no source-row list of m entries is set up.
 template <typename T>
 bool getf2_panel_cx(Ctx &c, long long m, int w, T *A, long long lda, long long off, int *ipiv);
 template <typename T>

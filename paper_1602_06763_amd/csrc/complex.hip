@@ -11,8 +11,9 @@
 //   - the complex product on the matrix cores: each complex multiply-add is
 //     four real ones, re += ar·br − ai·bi and im += ar·bi + ai·br, each a
 //     16×16×4 matrix-core step on the real and imaginary planes staged in LDS;
-//   - the triangular-solve leaf: a triangle of at most 64 rows in LDS, one
-//     right-hand side per thread, substitution;
+//   - the triangular-solve leaf: a triangle of at most 64 rows in LDS, 16
+//     right-hand sides per wave, the products between its 16-row blocks on
+//     the matrix cores and substitution within them;
 //   - the Cholesky leaf: a block of at most 64 in LDS, right-looking;
 //   - the LU leaf: a panel of at most 16 columns over all rows below its
 //     diagonal, one workgroup, the rows in global memory (the panel stays in
@@ -188,13 +189,21 @@ static void zgemm(Ctx &c, int opa, int opb, int tri, long long m, long long n, l
 // Triangular-solve leaf: N·x = b for nvec vectors, N the t×t (t <= 64)
 // triangle with N(i, j) = T[i·ti + j·tj] (conjugated when conj), lower or
 // upper, unit diagonal (taken as 1, not read) or not; element e of vector v
-// at B[e·se + v·sr]. One wave per workgroup, one vector per lane, the
-// triangle and the 64 vectors in LDS; substitution in the order of the
-// triangle.
+// at B[e·se + v·sr].
+//
+// 64 vectors per workgroup, 16 per wave; the triangle in LDS as real and
+// imaginary planes (zeros outside it, the identity beyond t), each wave's
+// vectors likewise. Blocks of 16 rows in the order of the solve: the product
+// with the blocks already solved on the matrix cores (the complex product as
+// four real 16×16×4 steps: re from ar·br and ai·bi, im from ar·bi + ai·br),
+// then the 16×16 diagonal block by substitution with four lanes per vector
+// (rows 4r..4r+3 of the block in lane r of the vector's quad), each solved
+// entry the quotient x·conj(p)/|p|² by its diagonal entry and handed to the
+// quad's other lanes by a broadcast.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct ZTrsmArgs {
-    int t, unit, conj, lower;
+    int t, unit, conj;
     long long ti, tj, nvec, se, sr;
     const cx<R> *T;
     cx<R> *B;
@@ -202,63 +211,131 @@ struct ZTrsmArgs {
     int abort;
 };
 
-template <typename R>
-__global__ __launch_bounds__(64) void ztrsm_leaf_k(ZTrsmArgs<R> a) {
+// element (e, q) of a wave's vectors that lane and step u move: along e when
+// it is contiguous (se = 1), along the vectors otherwise
+__device__ __forceinline__ void ztrsm_eq(bool se1, int lane, int u, int &e, int &q) {
+    if (se1) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
+    else { q = lane & 15; e = (lane >> 4) + 4 * u; }
+}
+
+template <typename R, bool LOWER>
+__global__ __launch_bounds__(256) void ztrsm_leaf_k(ZTrsmArgs<R> a) {
     if (a.abort && a.st->info) return;
-    __shared__ cx<R> Nsh[kZLeaf][kZLeaf + 1];
-    __shared__ cx<R> X[kZLeaf][kZLeaf + 1];   // X[e][lane]
-    const int lane = threadIdx.x, t = a.t;
-    const long long v0 = (long long)blockIdx.x * 64;
-    for (int idx = lane; idx < t * t; idx += 64) {
-        const int i = idx % t, j = idx / t;
-        const bool in = a.lower ? j < i : j > i;
-        cx<R> v{R(0), R(0)};
-        if (in || (i == j && !a.unit)) {
-            v = a.T[i * a.ti + j * a.tj];
+    typedef LeafMfma<R> Op;
+    typedef typename Op::acc_t acc_t;
+    __shared__ R Nre[64][65], Nim[64][65];
+    __shared__ R Xre[4][64][17], Xim[4][64][17];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, t = a.t;
+    const long long v0 = (long long)blockIdx.x * 64 + wave * 16;   // this wave's 16 vectors
+    R (*Xr)[17] = Xre[wave];
+    R (*Xi)[17] = Xim[wave];
+    const bool se1 = a.se == 1;
+    {
+        cx<R> tv[16], bv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
+            tv[u] = a.T[min(i, t - 1) * a.ti + min(j, t - 1) * a.tj];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int e, q;
+            ztrsm_eq(se1, lane, u, e, q);
+            bv[u] = a.B[min(e, t - 1) * a.se + min(v0 + q, a.nvec - 1) * a.sr];
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, i = idx % 64, j = idx / 64;
+            const bool in = i < t && j < t && (LOWER ? j < i : j > i);
+            cx<R> v = tv[u];
             if (a.conj) v.im = -v.im;
-        }
-        Nsh[i][j] = v;
-    }
-    // the vectors, loaded along whichever index is contiguous
-    if (a.se == 1) {
-        for (int idx = lane; idx < t * 64; idx += 64) {
-            const int e = idx % t, q = idx / t;
-            const long long v = v0 + q;
-            if (v < a.nvec) X[e][q] = a.B[e + v * a.sr];
-        }
-    } else {
-        for (int idx = lane; idx < t * 64; idx += 64) {
-            const int q = idx % 64, e = idx / 64;
-            const long long v = v0 + q;
-            if (v < a.nvec) X[e][q] = a.B[e * a.se + v];
-        }
-    }
-    __syncthreads();
-    if (v0 + lane < a.nvec) {
-        for (int s = 0; s < t; ++s) {
-            const int i = a.lower ? s : t - 1 - s;
-            cx<R> acc = X[i][lane];
-            if (a.lower) {
-                for (int j = 0; j < i; ++j) acc = csub(acc, cmul(Nsh[i][j], X[j][lane]));
-            } else {
-                for (int j = i + 1; j < t; ++j) acc = csub(acc, cmul(Nsh[i][j], X[j][lane]));
+            if (i == j) {
+                if (i >= t || a.unit) v = cx<R>{R(1), R(0)};
+            } else if (!in) {
+                v = cx<R>{R(0), R(0)};
             }
-            X[i][lane] = a.unit ? acc : cdiv(acc, Nsh[i][i]);
+            Nre[i][j] = v.re;
+            Nim[i][j] = v.im;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int e, q;
+            ztrsm_eq(se1, lane, u, e, q);
+            const bool ok = e < t && v0 + q < a.nvec;
+            Xr[e][q] = ok ? bv[u].re : R(0);
+            Xi[e][q] = ok ? bv[u].im : R(0);
         }
     }
     __syncthreads();
-    if (a.se == 1) {
-        for (int idx = lane; idx < t * 64; idx += 64) {
-            const int e = idx % t, q = idx / t;
-            const long long v = v0 + q;
-            if (v < a.nvec) a.B[e + v * a.sr] = X[e][q];
+
+    const int nblk = (t + 15) / 16;
+    for (int s = 0; s < nblk; ++s) {
+        const int I = LOWER ? s : nblk - 1 - s;
+        if (s > 0) {
+            // x_I -= Σ N_IJ·x_J over the blocks already solved
+            acc_t arr = acc_t{0, 0, 0, 0}, aii = acc_t{0, 0, 0, 0}, aim = acc_t{0, 0, 0, 0};
+            const int J0 = LOWER ? 0 : I + 1, J1 = LOWER ? I : nblk;
+            for (int J = J0; J < J1; ++J) {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = 16 * J + 4 * kk + (lane >> 4), r = 16 * I + (lane & 15);
+                    const R nr = Nre[r][k], ni = Nim[r][k], xr = Xr[k][lane & 15], xi = Xi[k][lane & 15];
+                    arr = Op::mma(nr, xr, arr);
+                    aii = Op::mma(ni, xi, aii);
+                    aim = Op::mma(nr, xi, aim);
+                    aim = Op::mma(ni, xr, aim);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * I + Op::row(lane, v);
+                Xr[r][lane & 15] -= arr[v] - aii[v];
+                Xi[r][lane & 15] -= aim[v];
+            }
+            __builtin_amdgcn_wave_barrier();
         }
-    } else {
-        for (int idx = lane; idx < t * 64; idx += 64) {
-            const int q = idx % 64, e = idx / 64;
-            const long long v = v0 + q;
-            if (v < a.nvec) a.B[e * a.se + v] = X[e][q];
+        {
+            const int v = lane >> 2, r4 = lane & 3, b0 = 16 * I;
+            R xr[4], xi[4];
+#pragma unroll
+            for (int t4 = 0; t4 < 4; ++t4) {
+                xr[t4] = Xr[b0 + 4 * r4 + t4][v];
+                xi[t4] = Xi[b0 + 4 * r4 + t4][v];
+            }
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) {
+                const int j = LOWER ? s2 : 15 - s2, jb = j >> 2, jj = j & 3;
+                const cx<R> p = cx<R>{Nre[b0 + j][b0 + j], Nim[b0 + j][b0 + j]};
+                const cx<R> xj = cx<R>{xr[jj], xi[jj]};
+                const cx<R> xs = a.unit ? xj : cdiv(xj, p);
+                const cx<R> xb = cx<R>{quad_bcast_sel(xs.re, jb), quad_bcast_sel(xs.im, jb)};
+#pragma unroll
+                for (int t4 = 0; t4 < 4; ++t4) {
+                    const int r = b0 + 4 * r4 + t4;
+                    const cx<R> f = csub(cx<R>{xr[t4], xi[t4]}, cmul(cx<R>{Nre[r][b0 + j], Nim[r][b0 + j]}, xb));
+                    // rows after j in the order of the solve take the update,
+                    // row j takes its solved value, the others stay
+                    const bool after = LOWER ? (t4 > jj ? r4 >= jb : r4 > jb) : (t4 < jj ? r4 <= jb : r4 < jb);
+                    const bool self = t4 == jj && r4 == jb;
+                    xr[t4] = after ? f.re : (self ? xs.re : xr[t4]);
+                    xi[t4] = after ? f.im : (self ? xs.im : xi[t4]);
+                }
+            }
+#pragma unroll
+            for (int t4 = 0; t4 < 4; ++t4) {
+                Xr[b0 + 4 * r4 + t4][v] = xr[t4];
+                Xi[b0 + 4 * r4 + t4][v] = xi[t4];
+            }
         }
+        __builtin_amdgcn_wave_barrier();
+    }
+
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        int e, q;
+        ztrsm_eq(se1, lane, u, e, q);
+        if (e < t && v0 + q < a.nvec) a.B[e * a.se + (v0 + q) * a.sr] = cx<R>{Xr[e][q], Xi[e][q]};
     }
 }
 
@@ -267,10 +344,13 @@ static void ztrsm_leaf(Ctx &c, bool lower, bool unit, bool conj, int t, const cx
                        long long nvec, cx<R> *B, long long se, long long sr) {
     if (plan_record(c, PK_ZLEAF, t, nvec, t)) return;
     if (t <= 0 || nvec <= 0) return;
-    ZTrsmArgs<R> a{t, unit ? 1 : 0, conj ? 1 : 0, lower ? 1 : 0, ti, tj, nvec, se, sr, T, B, c.dstat,
-                   c.abort_on_info ? 1 : 0};
+    ZTrsmArgs<R> a{t, unit ? 1 : 0, conj ? 1 : 0, ti, tj, nvec, se, sr, T, B, c.dstat, c.abort_on_info ? 1 : 0};
     trace_kernel_begin(c);
-    rl_launch(c, ztrsm_leaf_k<R>, dim3((unsigned)((nvec + 63) / 64)), dim3(64), 0, a);
+    const dim3 grid((unsigned)((nvec + 63) / 64));
+    if (lower)
+        rl_launch(c, ztrsm_leaf_k<R, true>, grid, dim3(256), 0, a);
+    else
+        rl_launch(c, ztrsm_leaf_k<R, false>, grid, dim3(256), 0, a);
     RL_CHECK(hipGetLastError());
     trace_kernel_end(c, PK_ZLEAF, 4.0 * t * t * nvec, 16.0 * (t * t / 2.0 + 2.0 * t * nvec));
 }
@@ -510,14 +590,18 @@ static void zgetrf_rec(Ctx &c, long long m, long long ncols, cx<R> *A, long long
                        long long w) {
     if (w <= kZLuLeaf) {
         if (plan_record(c, PK_ZLEAF, m - c0, w, w)) return;
-        // the cooperative panel (row blocks across the CUs); one workgroup
-        // when the chip cannot hold its grid
-        if (!getf2_panel_cx<cx<R>>(c, m, (int)w, A, lda, c0, ipiv)) {
-            trace_kernel_begin(c);
-            rl_launch(c, zgetf2_k<R>, dim3(1), dim3(1024), 0, m, (int)w, A, lda, c0, ipiv, c.dstat);
-            RL_CHECK(hipGetLastError());
-            trace_kernel_end(c, PK_ZLEAF, 8.0 * (m - c0) * w * w / 2.0, 32.0 * (m - c0) * w);
+        // the cooperative panel (row blocks across the CUs), its interchanges
+        // gathered into the other columns through its source-row list; one
+        // workgroup and the interchanges in order when the chip cannot hold
+        // the panel's grid
+        if (getf2_panel_cx<cx<R>>(c, m, (int)w, A, lda, c0, ipiv)) {
+            if (ncols > w) laswp_leaf<cx<R>>(c, A, lda, c0, (int)w, m, ipiv, 0, ncols);
+            return;
         }
+        trace_kernel_begin(c);
+        rl_launch(c, zgetf2_k<R>, dim3(1), dim3(1024), 0, m, (int)w, A, lda, c0, ipiv, c.dstat);
+        RL_CHECK(hipGetLastError());
+        trace_kernel_end(c, PK_ZLEAF, 8.0 * (m - c0) * w * w / 2.0, 32.0 * (m - c0) * w);
         if (ncols > w)
             hipLaunchKernelGGL(zlaswp_k<R>, dim3((unsigned)((ncols - w + 255) / 256)), dim3(256), 0, c.stream, ncols, c0,
                                (int)w, A, lda, (const int *)ipiv, c0, c0 + w);
@@ -547,6 +631,7 @@ void zgetrf_top(Ctx &c, long long m, long long n, void *Av, long long lda, int *
     cx<R> *A = (cx<R> *)Av;
     const long long mn = m < n ? m : n;
     if (mn <= 0) return;
+    c.lu_batch = false;   // interchanges go to the other columns after every panel
     zgetrf_rec<R>(c, m, n, A, lda, ipiv, 0, mn);
     if (n > m) ztrsm<R>(c, 'L', 'L', 0, true, m, n - m, A, lda, A + m * lda, lda);
 }

@@ -581,9 +581,9 @@ template void getf2_panel<float>(Ctx &, long long, int, float *, long long, long
 template <typename T>
 bool getf2_panel_cx(Ctx &c, long long m, int w, T *A, long long lda, long long c0, int *ipiv) {
     if (m - c0 <= 0 || w <= 0) return true;
-    // the complex recursion applies the interchanges to the other columns
-    // from ipiv itself (no source-row list)
-    return panel_launch<T>(c, m, w, A, lda, c0, ipiv, nullptr, PK_ZLEAF, 4.0 * (m - c0) * w * w, false);
+    // the source row of every position goes to rowsrc, for laswp_leaf
+    if (!c.rowsrc || c.rowsrc_elems < (size_t)m) return false;
+    return panel_launch<T>(c, m, w, A, lda, c0, ipiv, c.rowsrc, PK_ZLEAF, 4.0 * (m - c0) * w * w, false);
 }
 
 template bool getf2_panel_cx<cx<double>>(Ctx &, long long, int, cx<double> *, long long, long long, int *);
@@ -673,6 +673,10 @@ template void laswp_leaf<double>(Ctx &, double *, long long, long long, int, lon
                                  long long);
 template void laswp_leaf<float>(Ctx &, float *, long long, long long, int, long long, const int *, long long,
                                 long long);
+template void laswp_leaf<cx<double>>(Ctx &, cx<double> *, long long, long long, int, long long, const int *,
+                                     long long, long long);
+template void laswp_leaf<cx<float>>(Ctx &, cx<float> *, long long, long long, int, long long, const int *,
+                                    long long, long long);
 
 // ---------------------------------------------------------------------------
 // Batched interchanges (the recursion's own order: after one half is factored
