@@ -265,7 +265,10 @@ void relapack_dtrsm(char side, char uplo, char transa, char diag, int m, int n, 
  * Sec. 3, Fig. recursive_alg): B := alpha·op(A)·B (side 'L', A m×m) or
  * B := alpha·B·op(A) (side 'R', A n×n); A triangular (uplo), unit diagonal if
  * diag = 'U' (then its diagonal is not read). B: m×n, overwritten. Recursive
- * down to a 64×64 matrix-core leaf.
+ * down to triangles of at most 1024 rows, each then one launch over a copy
+ * of its part of B (library workspace, grown on demand, kept until
+ * relapack_finalize), or a 64×64 matrix-core leaf for triangles of at most
+ * 64 rows.
  * Errors: side -1, uplo -2, transa -3, diag -4, m -5, n -6, lda -9, ldb -11.
  */
 void relapack_dtrmm(char side, char uplo, char transa, char diag, int m, int n, double alpha,
@@ -418,7 +421,9 @@ void relapack_trace_enable(int on);
  * 3 gemm on 64×64 tiles and 12 gemm on 128×128 tiles, 4 syrk (FP64 matrix
  * cores), 5 getf2 panel, 6 laswp, 7 convert, 8 residual, 10 gemm and 11 syrk
  * with FP32/FP16/BF16 operands, 13 triangular-inverse leaf, 14 trmm leaf,
- * 15 lauum leaf. Single-kernel families are timed by the
+ * 15 lauum leaf, 16 complex products, 17 complex leaves, 18 trmm of a whole
+ * triangle in one launch (with its copy of B). Single-kernel families are
+ * timed by the
  * kernel's own start/end timestamps, the others by events around them.
  * Synchronizes the stream and clears the records. Returns cap, or -1 on a
  * HIP error. */

@@ -85,7 +85,7 @@ _SIGS = {
 
 TRACE_FAMILIES = {1: "potf2", 2: "trsm_leaf", 3: "gemm", 4: "syrk", 5: "getf2_panel", 6: "laswp",
                   7: "convert", 8: "residual", 10: "gemm_lowprec", 11: "syrk_lowprec", 12: "gemm128",
-                  13: "trti2", 14: "trmm_leaf", 15: "lauu2", 16: "zgemm", 17: "complex_leaf"}
+                  13: "trti2", 14: "trmm_leaf", 15: "lauu2", 16: "zgemm", 17: "complex_leaf", 18: "trmm"}
 
 PREC = {"fp32": 32, "32": 32, 32: 32, "fp16": 16, "16": 16, 16: 16, "bf16": ord("b"), "b": ord("b")}
 
@@ -500,7 +500,7 @@ def trace_enable(on: bool = True) -> None:
 
 
 def trace_collect() -> dict:
-    cap = 18
+    cap = 19
     out = (ctypes.c_double * (4 * cap))()
     if lib().relapack_trace_collect(out, cap) < 0:
         raise RuntimeError("relapack_trace_collect failed")

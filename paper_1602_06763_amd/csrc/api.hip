@@ -13,8 +13,9 @@ namespace rl {
 namespace {
 
 constexpr int kMaxDev = 16;
-constexpr int kScratchSlots = 11;   // 0-6 mixed solver, 7 LU row tracker, 8 correction-solve block inverses,
-                                    // 9 launch order of a batch, 10 GMRES basis
+constexpr int kScratchSlots = 12;   // 0-6 mixed solver, 7 LU row tracker, 8 correction-solve block inverses,
+                                    // 9 launch order of a batch, 10 GMRES basis, 11 copy of a
+                                    // triangular product's right-hand block
 
 struct DevState {
     bool init = false;

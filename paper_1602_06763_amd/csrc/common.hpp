@@ -62,7 +62,8 @@ enum PlanKind : int {
     PK_GEMM_BIG = 12,  // FP64 GEMM launches on 128×128 tiles (traced separately from PK_GEMM)
     PK_TRTI2 = 13, PK_TRMM_LEAF = 14, PK_LAUU2 = 15,
     PK_ZGEMM = 16,   // complex products on the matrix cores
-    PK_ZLEAF = 17    // complex leaves (Cholesky block, triangular-solve leaf, LU panel)
+    PK_ZLEAF = 17,   // complex leaves (Cholesky block, triangular-solve leaf, LU panel)
+    PK_TRMM = 18     // triangular product of a whole triangle in one launch
 };
 
 // Workspace that a caller-free entry point brings in from a fixed device
@@ -130,6 +131,7 @@ Ctx &ctx();
 void ensure_device(Ctx &c);
 void *workspace(Ctx &c, int slot, size_t bytes);   // grow-only per-device workspace
 constexpr int kSlotBatchOrder = 9;                 // workspace slot: launch order of a batch
+constexpr int kSlotTrmm = 11;                      // workspace slot: copy of a triangular product's B
 // Exchange records of the cooperative LU panel ([kLuLeaf][kRecSlots][kRecWords]
 // words) and the first of kLuLeaf consecutive epochs reserved for one panel.
 unsigned long long *panel_records(Ctx &c, unsigned int *epoch);

@@ -133,6 +133,166 @@ static void trmm_leaf(Ctx &c, bool lower_eff, bool unit, int t, const double *T,
     trace_kernel_end(c, PK_TRMM_LEAF, (double)t * t * nvec, 8.0 * (t * t / 2.0 + 2.0 * t * nvec));
 }
 
+// ---------------------------------------------------------------------------
+// Triangular product of a whole triangle in one launch (triangles of more
+// than one leaf and at most kTrmmBlk rows): y := α·N·x for every vector, N
+// the t×t triangle (LOWER: j <= i) as in trmm_leaf_k, x read from a copy of B
+// in workspace (element e of vector r at X[e*xe + r*xr]) so that the output
+// tiles of one launch are independent. A workgroup takes 64 rows × 64
+// vectors, four waves of 32×32 on the FP64 matrix cores; K runs over the
+// tile's part of the triangle only (k <= i for a lower N, k >= i for an
+// upper one), 16 at a time, double-buffered through LDS. The K step that
+// crosses the diagonal stages zeros outside the triangle (and 1 on a unit
+// diagonal, which is not read). Heaviest tile rows are dealt first.
+// ---------------------------------------------------------------------------
+constexpr int kTrmmBlk = 1024;
+
+struct TrmmBlkArgs {
+    int unit, t, tiles_e;
+    const double *T;
+    long long ti, tj;
+    const double *X;
+    long long xe, xr;
+    double *B;
+    long long se, sr, nvec;
+    double alpha;
+    const int *abort;
+};
+
+template <bool LOWER>
+__global__ __launch_bounds__(256) void trmm_blk_k(TrmmBlkArgs a) {
+    if (a.abort && *a.abort) return;
+    __shared__ double Ns[2][16][65];   // [k][row]
+    __shared__ double Xs[2][16][65];   // [k][vector]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, t = a.t;
+    const int rt = (int)(blockIdx.x % a.tiles_e);
+    const int te = LOWER ? a.tiles_e - 1 - rt : rt;
+    const long long v0 = (long long)(blockIdx.x / a.tiles_e) * 64;
+    const int e0 = 64 * te;
+    const int kb = LOWER ? 0 : e0, ke = LOWER ? min(e0 + 64, t) : t;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const bool tcol = a.ti == 1, xcol = a.xe == 1;   // contiguous along the rows / along k
+    double rn[4], rx[4];
+    auto n_coord = [&](int u, int &i, int &k) {
+        if (tcol) { i = tid & 63; k = (tid >> 6) + 4 * u; }
+        else { k = tid & 15; i = (tid >> 4) + 16 * u; }
+    };
+    auto x_coord = [&](int u, int &k, int &v) {
+        if (xcol) { k = tid & 15; v = (tid >> 4) + 16 * u; }
+        else { v = tid & 63; k = (tid >> 6) + 4 * u; }
+    };
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int i, k;
+            n_coord(u, i, k);
+            const int gi = e0 + i, gk = k0 + k;
+            const bool in = gi < t && gk < t && (LOWER ? gk <= gi : gk >= gi);
+            rn[u] = !in ? 0.0 : ((gk == gi && a.unit) ? 1.0 : a.T[gi * a.ti + gk * a.tj]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int k, v;
+            x_coord(u, k, v);
+            const int gk = k0 + k;
+            const long long gv = v0 + v;
+            rx[u] = (gk < ke && gv < a.nvec) ? a.X[gk * a.xe + gv * a.xr] : 0.0;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int i, k;
+            n_coord(u, i, k);
+            Ns[buf][k][i] = rn[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int k, v;
+            x_coord(u, k, v);
+            Xs[buf][k][v] = rx[u];
+        }
+    };
+    d4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0, 0, 0, 0};
+    const int KT = (ke - kb + 15) / 16;   // >= 1
+    load(kb);
+    store(0);
+    __syncthreads();
+    for (int kt = 0; kt < KT; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < KT) load(kb + 16 * (kt + 1));
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kr = 4 * ks + (lane >> 4);
+            double av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) av[i] = Ns[buf][kr][wm + 16 * i + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bv[j] = Xs[buf][kr][wn + 16 * j + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+        if (kt + 1 < KT) store(buf ^ 1);
+        __syncthreads();
+    }
+    // FP64 16×16×4 result layout: element v of lane l is D[l/16 + 4v][l%16]
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int e = e0 + wm + 16 * i + (lane >> 4) + 4 * v;
+                const long long r = v0 + wn + 16 * j + (lane & 15);
+                if (e < t && r < a.nvec) a.B[e * a.se + r * a.sr] = a.alpha * acc[i][j][v];
+            }
+}
+
+// X := B (t elements of nvec vectors), contiguous along whichever index B is
+__global__ __launch_bounds__(256) void trmm_copy_k(const double *__restrict__ B, long long se, long long sr,
+                                                   double *__restrict__ X, int t, long long nvec, const int *abort) {
+    if (abort && *abort) return;
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (long long)t * nvec) return;
+    if (se == 1) {
+        const long long e = idx % t, r = idx / t;
+        X[idx] = B[e + r * sr];
+    } else {
+        const long long r = idx % nvec, e = idx / nvec;
+        X[idx] = B[e * se + r];
+    }
+}
+
+static void trmm_blk(Ctx &c, bool lower_eff, bool unit, int t, const double *T, long long ti, long long tj,
+                     long long nvec, double *B, long long se, long long sr, double alpha) {
+    if (plan_record(c, PK_TRMM, t, nvec, t)) return;
+    if (t <= 0 || nvec <= 0) return;
+    double *X = (double *)workspace(c, kSlotTrmm, (size_t)t * (size_t)nvec * sizeof(double));
+    if (!X) return;
+    const int *abort = c.abort_on_info ? &c.dstat->info : nullptr;
+    trace_begin(c, PK_TRMM);
+    const long long nel = (long long)t * nvec;
+    hipLaunchKernelGGL(trmm_copy_k, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, c.stream, B, se, sr, X, t,
+                       nvec, abort);
+    RL_CHECK(hipGetLastError());
+    TrmmBlkArgs a{unit ? 1 : 0, t, (t + 63) / 64, T, ti, tj, X, se == 1 ? 1 : nvec, se == 1 ? (long long)t : 1,
+                  B, se, sr, nvec, alpha, abort};
+    const dim3 grid((unsigned)((long long)a.tiles_e * ((nvec + 63) / 64)));
+    if (lower_eff)
+        hipLaunchKernelGGL(trmm_blk_k<true>, grid, dim3(256), 0, c.stream, a);
+    else
+        hipLaunchKernelGGL(trmm_blk_k<false>, grid, dim3(256), 0, c.stream, a);
+    RL_CHECK(hipGetLastError());
+    trace_end(c, PK_TRMM, (double)t * t * nvec, 8.0 * (t * t / 2.0 + 3.0 * t * nvec));
+}
+
 // Pointer to the block op(T)[r0:, c0:] in storage.
 static inline const double *opblk(const double *T, long long ldt, bool trans, long long r0, long long c0) {
     return trans ? T + c0 + r0 * ldt : T + r0 + c0 * ldt;
@@ -155,6 +315,10 @@ void trmm(Ctx &c, char side, char uplo, char trans, char diag, long long m, long
             trmm_leaf(c, lowerM, unit, (int)m, T, tr ? ldt : 1, tr ? 1 : ldt, n, B, 1, ldb, alpha);
             return;
         }
+        if (m <= kTrmmBlk) {
+            trmm_blk(c, lowerM, unit, (int)m, T, tr ? ldt : 1, tr ? 1 : ldt, n, B, 1, ldb, alpha);
+            return;
+        }
         const long long m1 = split_size(m), m2 = m - m1;
         const double *T22 = T + m1 + m1 * ldt;
         if (lowerM) {
@@ -174,6 +338,10 @@ void trmm(Ctx &c, char side, char uplo, char trans, char diag, long long m, long
         if (n <= leaf) {
             // row r of B: b_r := α·b_r·op(T), i.e. y = α·op(T)ᵀ·x
             trmm_leaf(c, !lowerM, unit, (int)n, T, tr ? 1 : ldt, tr ? ldt : 1, m, B, ldb, 1, alpha);
+            return;
+        }
+        if (n <= kTrmmBlk) {
+            trmm_blk(c, !lowerM, unit, (int)n, T, tr ? 1 : ldt, tr ? ldt : 1, m, B, ldb, 1, alpha);
             return;
         }
         const long long n1 = split_size(n), n2 = n - n1;

@@ -26,8 +26,11 @@ def _tri(uplo):
 @pytest.mark.parametrize("uplo", ["L", "U"])
 @pytest.mark.parametrize("trans", ["N", "T"])
 @pytest.mark.parametrize("diag", ["N", "U"])
-@pytest.mark.parametrize("m,n", [(1, 1), (64, 64), (65, 33), (200, 130)])
+@pytest.mark.parametrize("m,n", [(1, 1), (64, 64), (65, 33), (200, 130), (300, 257), (1030, 90)])
 def test_trmm(side, uplo, trans, diag, m, n):
+    """Up to 64 rows the leaf; above, one launch per triangle of up to 1024
+    rows (ragged tiles at 200, 257, 300) under the recursion's splits
+    (1030)."""
     t = m if side == "L" else n
     tri = gen.triangular(t, uplo, "N", seed=t)
     stored = tri.copy(order="F")
@@ -47,7 +50,7 @@ def test_trmm(side, uplo, trans, diag, m, n):
     assert (err <= 4 * (t + 2) * U64 * scale + 1e-300).all()
 
 
-@pytest.mark.parametrize("n", [1, 17, 64, 65, 200, 517])
+@pytest.mark.parametrize("n", [1, 17, 64, 65, 200, 517, 1500, 2300])
 @pytest.mark.parametrize("uplo", ["L", "U"])
 @pytest.mark.parametrize("diag", ["N", "U"])
 def test_trtri_vs_oracle(n, uplo, diag):
@@ -93,7 +96,7 @@ def test_trtri_zero_pivot(uplo):
     assert rl.trtri(A, uplo, "U") == 0   # a unit diagonal is not inspected
 
 
-@pytest.mark.parametrize("n", [1, 33, 64, 65, 300, 517])
+@pytest.mark.parametrize("n", [1, 33, 64, 65, 300, 517, 1500, 2300])
 @pytest.mark.parametrize("uplo", ["L", "U"])
 def test_lauum_vs_oracle(n, uplo):
     t = gen.triangular(n, uplo, "N", seed=n + 2) / n
