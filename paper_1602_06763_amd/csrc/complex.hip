@@ -14,7 +14,8 @@
 //   - the triangular-solve leaf: a triangle of at most 64 rows in LDS, 16
 //     right-hand sides per wave, the products between its 16-row blocks on
 //     the matrix cores and substitution within them;
-//   - the Cholesky leaf: a block of at most 64 in LDS, right-looking;
+//   - the Cholesky leaf: a block of at most 64 in LDS, 16-column panels by
+//     one wave, the trailing updates on the matrix cores;
 //   - the LU leaf: a panel of at most 16 columns over all rows below its
 //     diagonal, one workgroup, the rows in global memory (the panel stays in
 //     L2), and its interchanges applied at once to every other column.
@@ -407,58 +408,124 @@ static void ztrsm(Ctx &c, char side, char uplo, int trans, bool unit, long long 
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky leaf: a Hermitian block of n <= 64 in LDS, one workgroup,
-// right-looking: l_kk = sqrt(re(a_kk)) (not > 0 or NaN: the first failing
-// column off+k+1 into info, the block written back as it stands), the column
-// divided by it, the trailing triangle updated by a_ij -= l_ik·conj(l_jk).
-// For 'U' the block is read as L = Uᴴ and written back conjugate-transposed.
+// Cholesky leaf: a Hermitian block of n <= 64 in LDS (real and imaginary
+// planes, the identity beyond n), one workgroup: l_kk = sqrt(re(a_kk)) (not
+// > 0 or NaN: the first failing column off+k+1 into info, the block written
+// back as it stands), the column divided by it, the trailing triangle
+// updated by a_ij -= l_ik·conj(l_jk). For 'U' the block is read as L = Uᴴ and
+// written back conjugate-transposed.
+//
+// The 64 columns go 16 at a time: one wave factors the 16-column panel (lane
+// = row, the row's 16 entries in registers, the steps unrolled; each step's
+// l_jk of the panel's own rows reach the other lanes by readlane), then all
+// four waves subtract the panel's l_ik·conj(l_jk) from the trailing lower
+// triangle on the matrix cores, the complex product as four real 16×16×4
+// steps (re from lr·lr + li·li, im from li·lr − lr·li).
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ __launch_bounds__(256) void zpotf2_k(int n, cx<R> *A, long long lda, int upper, long long off,
                                                 DevStatus *st) {
     if (st->info) return;
-    __shared__ cx<R> S[kZLeaf][kZLeaf + 1];
+    typedef LeafMfma<R> Op;
+    typedef typename Op::acc_t acc_t;
+    __shared__ R Sr[kZLeaf][kZLeaf + 1], Si[kZLeaf][kZLeaf + 1];
     __shared__ int fail_s;
-    const int tid = threadIdx.x;
-    for (int idx = tid; idx < n * n; idx += 256) {
-        const int i = idx % n, j = idx / n;
-        if (j <= i) {
-            cx<R> v = upper ? A[j + (long long)i * lda] : A[i + (long long)j * lda];
-            if (upper) v.im = -v.im;
-            S[i][j] = v;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    {
+        cx<R> v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = min(lane, n - 1), j = min(wave + 4 * u, n - 1);
+            v[u] = upper ? A[j + (long long)i * lda] : A[i + (long long)j * lda];
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = lane, j = wave + 4 * u;
+            const bool in = i < n && j < n;
+            const R im = upper ? -v[u].im : v[u].im;
+            Sr[i][j] = in ? (j <= i ? v[u].re : R(0)) : (i == j ? R(1) : R(0));
+            Si[i][j] = in && j <= i ? im : R(0);
         }
     }
     if (tid == 0) fail_s = 0;
     __syncthreads();
-    int k = 0;
-    for (; k < n; ++k) {
-        if (tid == 0) {
-            const R d = S[k][k].re;
-            if (!(d > R(0))) fail_s = k + 1;
-            else S[k][k] = cx<R>{sqrt(d), R(0)};
+    const int nb = (n + 15) / 16;
+    for (int J = 0; J < nb; ++J) {
+        const int c0 = 16 * J;
+        if (wave == 0) {
+            const int r = lane;
+            R xr[16], xi[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                xr[q] = Sr[r][c0 + q];
+                xi[q] = Si[r][c0 + q];
+            }
+            int fail = 0;
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                const int k = c0 + kk;
+                if (fail == 0 && k < n) {
+                    const R d = lane_bcast(xr[kk], k);
+                    if (!(d > R(0))) {
+                        fail = k + 1;
+                    } else {
+                        const R lkk = sqrt(d);
+                        R lr = xr[kk] / lkk, li = xi[kk] / lkk;
+                        if (r == k) { lr = lkk; li = R(0); }
+                        if (r >= k) { xr[kk] = lr; xi[kk] = li; }
+#pragma unroll
+                        for (int q = kk + 1; q < 16; ++q) {
+                            // a_rq -= l_rk·conj(l_qk), l_qk from lane c0 + q
+                            const R cr = lane_bcast(lr, c0 + q), ci = lane_bcast(li, c0 + q);
+                            xr[q] -= lr * cr + li * ci;
+                            xi[q] -= li * cr - lr * ci;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                Sr[r][c0 + q] = xr[q];
+                Si[r][c0 + q] = xi[q];
+            }
+            if (r == 0) fail_s = fail;
         }
         __syncthreads();
         if (fail_s) break;
-        const R lkk = S[k][k].re;
-        for (int i = k + 1 + tid; i < n; i += 256) S[i][k] = cx<R>{S[i][k].re / lkk, S[i][k].im / lkk};
-        __syncthreads();
-        const int r = n - k - 1;
-        for (int idx = tid; idx < r * r; idx += 256) {
-            const int i = k + 1 + idx % r, j = k + 1 + idx / r;
-            if (j <= i) S[i][j] = csub(S[i][j], cmul(S[i][k], cconj(S[j][k])));
+        // trailing lower triangle: tiles (I, Jt) with J < Jt <= I < nb
+        const int m = nb - 1 - J;
+        const int ntiles = m * (m + 1) / 2;
+        for (int tt = wave; tt < ntiles; tt += 4) {
+            int I = 0, acc0 = 0;
+            while (acc0 + I + 1 <= tt) { acc0 += I + 1; ++I; }
+            const int i0 = 16 * (J + 1 + I), j0 = 16 * (J + 1 + tt - acc0);
+            acc_t are = acc_t{0, 0, 0, 0}, aim = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int c = c0 + 4 * kk + (lane >> 4);
+                const R ar = Sr[i0 + (lane & 15)][c], ai = Si[i0 + (lane & 15)][c];
+                const R br = Sr[j0 + (lane & 15)][c], bi = Si[j0 + (lane & 15)][c];
+                are = Op::mma(ar, br, are);
+                are = Op::mma(ai, bi, are);
+                aim = Op::mma(ai, br, aim);
+                aim = Op::mma(-ar, bi, aim);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + Op::row(lane, v), j = j0 + (lane & 15);
+                Sr[i][j] -= are[v];
+                Si[i][j] -= aim[v];
+            }
         }
         __syncthreads();
     }
-    for (int idx = tid; idx < n * n; idx += 256) {
-        const int i = idx % n, j = idx / n;
-        if (j <= i) {
-            cx<R> v = S[i][j];
-            if (upper) {
-                v.im = -v.im;
-                A[j + (long long)i * lda] = v;
-            } else {
-                A[i + (long long)j * lda] = v;
-            }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int i = lane, j = wave + 4 * u;
+        if (i < n && j <= i) {
+            if (upper) A[j + (long long)i * lda] = cx<R>{Sr[i][j], -Si[i][j]};
+            else A[i + (long long)j * lda] = cx<R>{Sr[i][j], Si[i][j]};
         }
     }
     if (tid == 0 && fail_s) atomicCAS(&st->info, 0, (int)(off + fail_s));
