@@ -200,6 +200,10 @@ void getrf_top(Ctx &c, Mfma mode, long long m, long long n, T *A, long long lda,
 // Leaf kernels.
 template <typename T>
 void potf2(Ctx &c, char uplo, int n, T *A, long long lda, long long off);
+// The recursion's bottom node (64 < n <= 128: potf2, solve, update, potf2)
+// in one launch.
+template <typename T>
+void potf2x2(Ctx &c, char uplo, int n, T *A, long long lda, long long off);
 template <typename TT, typename TB>
 void trsm_leaf(Ctx &c, bool lower_eff, bool unit, int t, const TT *T, long long ti, long long tj,
                long long nvec, TB *B, long long se, long long sr);

@@ -23,6 +23,15 @@ void potrf_rec(Ctx &c, Mfma mode, char uplo, long long n, T *A, long long lda, l
         potf2<T>(c, uplo, (int)n, A, lda, off);
         return;
     }
+    // the bottom node in one launch, where its update runs in the working
+    // precision (not the mixed solver's FP16/BF16 operands) and no plan asks
+    // for another leaf size (a plan with an explicit crossover records the
+    // plain recursion at that crossover)
+    const bool native = mode == (sizeof(T) == 8 ? Mfma::F64 : Mfma::F32);
+    if (native && !(c.plan && c.plan_leaf > 0) && n <= 2 * kCholLeaf) {
+        potf2x2<T>(c, uplo, (int)n, A, lda, off);
+        return;
+    }
     const long long n1 = split_size(n), n2 = n - n1;
     const bool lower = (uplo == 'L' || uplo == 'l');
     T *A11 = A, *A22 = A + n1 + n1 * lda;

@@ -35,6 +35,100 @@ __global__ __launch_bounds__(256) void potf2_k(int n, T *__restrict__ A, long lo
     if (fail && threadIdx.x == 0) atomicCAS(&st->info, 0, (int)(off + fail));
 }
 
+// ---------------------------------------------------------------------------
+// The bottom node of the recursion, 64 < n <= 128, in one launch: the same
+// steps as the recursion takes there (split n1 = split_size(n), n2 = n - n1,
+// both <= 64), each on LDS: potf2 of A11 (potf2_factor); A21 := A21·L11⁻ᵀ by
+// the triangular-solve leaf's substitution (solve64, the rows of A21 as the
+// right-hand sides, 16 per wave); A22 -= L21·L21ᵀ on the matrix cores over
+// the whole K range in order, as the GEMM kernel sums it; potf2 of A22. A
+// failing pivot in A11 leaves A21 and A22 untouched, as the recursion's later
+// kernels do when they see info set.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void potf2x2_k(int n, T *__restrict__ A, long long lda, int upper,
+                                                 long long off, DevStatus *st) {
+    if (st->info) return;
+    typedef LeafMfma<T> Op;
+    typedef typename Op::acc_t acc_t;
+    __shared__ Potf2Lds<T> L1, L2;
+    __shared__ T X[4][64][17];   // A21: row n1 + 16w + q of the block, column e at X[w][e][q]
+    const long long si = upper ? lda : 1, sj = upper ? 1 : lda;
+    const int n1 = (int)split_size(n), n2 = n - n1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    T *A21 = A + n1 * si, *A22 = A + n1 * si + n1 * sj;
+    potf2_stage(n1, A, si, sj, L1.S);
+    potf2_stage(n2, A22, si, sj, L2.S);
+    {
+        T v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int e, q;
+            if (upper) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
+            else { q = lane & 15; e = (lane >> 4) + 4 * u; }
+            const int r = 16 * wave + q;
+            v[u] = A21[min(r, n2 - 1) * si + min(e, n1 - 1) * sj];
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int e, q;
+            if (upper) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
+            else { q = lane & 15; e = (lane >> 4) + 4 * u; }
+            X[wave][e][q] = (16 * wave + q < n2 && e < n1) ? v[u] : T(0);
+        }
+    }
+    if (tid == 0) { L1.fail_s = 0; L2.fail_s = 0; }
+    __syncthreads();
+    const int f1 = potf2_factor(n1, L1);
+    if (f1) {
+        potf2_store(n1, A, si, sj, L1.S);
+        if (tid == 0) atomicCAS(&st->info, 0, (int)(off + f1));
+        return;
+    }
+    solve64<T, true>(L1.S, X[wave], n1, 0, lane);
+    __syncthreads();
+    // A22 -= L21·L21ᵀ, lower 16×16 tiles (I, J), J <= I
+    for (int tt = wave; tt < 10; tt += 4) {
+        int I = 0, a0 = 0;
+        while (a0 + I + 1 <= tt) { a0 += I + 1; ++I; }
+        const int J = tt - a0;
+        acc_t acc = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int k4 = 0; k4 < 16; ++k4) {
+            const int k = 4 * k4 + (lane >> 4);
+            acc = Op::mma(X[I][k][lane & 15], X[J][k][lane & 15], acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) L2.S[16 * I + Op::row(lane, v)][16 * J + (lane & 15)] -= acc[v];
+    }
+    __syncthreads();
+    const int f2 = potf2_factor(n2, L2);
+    potf2_store(n1, A, si, sj, L1.S);
+    potf2_store(n2, A22, si, sj, L2.S);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        int e, q;
+        if (upper) { e = (lane & 15) + 16 * (u & 3); q = (lane >> 4) + 4 * (u >> 2); }
+        else { q = lane & 15; e = (lane >> 4) + 4 * u; }
+        const int r = 16 * wave + q;
+        if (r < n2 && e < n1) A21[r * si + e * sj] = X[wave][e][q];
+    }
+    if (f2 && tid == 0) atomicCAS(&st->info, 0, (int)(off + n1 + f2));
+}
+
+template <typename T>
+void potf2x2(Ctx &c, char uplo, int n, T *A, long long lda, long long off) {
+    if (plan_record(c, PK_POTF2, n, n, n)) return;
+    trace_kernel_begin(c);
+    rl_launch(c, potf2x2_k<T>, dim3(1), dim3(256), 0, n, A, lda, (int)(uplo == 'U' || uplo == 'u'), off, c.dstat);
+    RL_CHECK(hipGetLastError());
+    trace_kernel_end(c, PK_POTF2, (double)n * n * n / 3.0, 8.0 * n * n);
+}
+
+template void potf2x2<double>(Ctx &, char, int, double *, long long, long long);
+template void potf2x2<float>(Ctx &, char, int, float *, long long, long long);
+
 template <typename T>
 void potf2(Ctx &c, char uplo, int n, T *A, long long lda, long long off) {
     if (plan_record(c, PK_POTF2, n, n, n)) return;

@@ -208,30 +208,48 @@ struct Potf2Lds {
 // scaling off the step-to-step dependency chain; the panel's columns are
 // scaled to l_rk = a_rk / sqrt(a_kk) by all waves once the panel is done.
 // ---------------------------------------------------------------------------
+// Stage the n×n block (element (i, j) of the lower factor at A[i*si + j*sj])
+// into S: its lower triangle, zeros above, the identity beyond n.
 template <typename T>
-__device__ __forceinline__ int potf2_block(int n, T *__restrict__ A, long long si, long long sj, Potf2Lds<T> &L) {
+__device__ __forceinline__ void potf2_stage(int n, const T *__restrict__ A, long long si, long long sj,
+                                            T (*S)[65]) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    T v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int i = lane, j = wave + 4 * u;
+        v[u] = A[min(i, n - 1) * si + min(j, n - 1) * sj];
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int i = lane, j = wave + 4 * u;
+        // lower triangle; rows and columns past n are the identity
+        S[i][j] = (i < n && j < n) ? (j <= i ? v[u] : T(0)) : (i == j ? T(1) : T(0));
+    }
+}
+
+// Write back the lower triangle of the n×n block from S.
+template <typename T>
+__device__ __forceinline__ void potf2_store(int n, T *__restrict__ A, long long si, long long sj, T (*S)[65]) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int i = lane, j = wave + 4 * u;
+        if (i < n && j <= i) A[i * si + j * sj] = S[i][j];
+    }
+}
+
+// The factorization of a block staged in L.S (L.fail_s = 0 and a barrier
+// before the call); every thread of the workgroup returns the same value
+// after a final barrier.
+template <typename T>
+__device__ __forceinline__ int potf2_factor(int n, Potf2Lds<T> &L) {
     T (*S)[65] = L.S;
     T (&cb)[2][16] = L.cb;
     T (&dd)[16] = L.dd;
     int &fail_s = L.fail_s;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    {
-        T v[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int i = lane, j = wave + 4 * u;
-            v[u] = A[min(i, n - 1) * si + min(j, n - 1) * sj];
-        }
-        asm volatile("" ::: "memory");
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int i = lane, j = wave + 4 * u;
-            // lower triangle; rows and columns past n are the identity
-            S[i][j] = (i < n && j < n) ? (j <= i ? v[u] : T(0)) : (i == j ? T(1) : T(0));
-        }
-    }
-    if (tid == 0) fail_s = 0;
-    __syncthreads();
     const int nb = (n + 15) / 16;
     for (int J = 0; J < nb; ++J) {
         if (wave == 0) {
@@ -297,13 +315,16 @@ __device__ __forceinline__ int potf2_block(int n, T *__restrict__ A, long long s
         }
         __syncthreads();
     }
-    const int fail = fail_s;
-    // write back the lower triangle
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const int i = lane, j = wave + 4 * u;
-        if (i < n && j <= i) A[i * si + j * sj] = S[i][j];
-    }
+    return fail_s;
+}
+
+template <typename T>
+__device__ __forceinline__ int potf2_block(int n, T *__restrict__ A, long long si, long long sj, Potf2Lds<T> &L) {
+    potf2_stage(n, A, si, sj, L.S);
+    if (threadIdx.x == 0) L.fail_s = 0;
+    __syncthreads();
+    const int fail = potf2_factor(n, L);
+    potf2_store(n, A, si, sj, L.S);
     return fail;
 }
 
