@@ -31,6 +31,7 @@
 //  * diag_zero_k: the first exact zero on the diagonal (LAPACK reports it
 //    before inverting anything); every later kernel of the call then skips.
 #include "common.hpp"
+#include "wg.hpp"
 
 namespace rl {
 
@@ -422,6 +423,194 @@ static void lauu2(Ctx &c, bool lower, int t, double *A, long long lda) {
 }
 
 // ---------------------------------------------------------------------------
+// The inversion's bottom node (64 < n <= 128) in one launch: the four steps
+// of Fig. recursive_alg on LDS, with n1 = split_size(n), n2 = n - n1 (both
+// <= 64) and the triangle read as lower (an upper one as its transpose, whose
+// inverse is the transpose of the inverse):
+//   (1) A11 := A11⁻¹          the leaf solve against the identity (solve64);
+//   (2) A21 := −A21·A11⁻¹     on the matrix cores;
+//   (3) A21 := A22⁻¹·A21      the leaf solve with the original A22;
+//   (4) A22 := A22⁻¹          the leaf solve against the identity.
+// A unit diagonal is taken as 1 and neither read nor written.
+// ---------------------------------------------------------------------------
+template <bool LOWER>
+__global__ __launch_bounds__(256) void trtri128_k(int n, int unit, double *__restrict__ A, long long lda,
+                                                  const int *abort) {
+    if (abort && *abort) return;
+    __shared__ double N1[64][65], N2[64][65], S21[64][65];
+    __shared__ double X[4][64][17];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n1 = (int)split_size(n), n2 = n - n1;
+    // element (i, j) of the lower view: A[i·si + j·sj]
+    const long long si = LOWER ? 1 : lda, sj = LOWER ? lda : 1;
+    double *A21 = A + n1 * si, *A22 = A + n1 * si + n1 * sj;
+    {
+        double a[16], b[16], c[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, p = idx & 63, q = idx >> 6;
+            const int i = LOWER ? p : q, j = LOWER ? q : p;   // the contiguous index across the threads
+            a[u] = A[min(i, n1 - 1) * si + min(j, n1 - 1) * sj];
+            b[u] = A22[min(i, n2 - 1) * si + min(j, n2 - 1) * sj];
+            c[u] = A21[min(i, n2 - 1) * si + min(j, n1 - 1) * sj];
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u, p = idx & 63, q = idx >> 6;
+            const int i = LOWER ? p : q, j = LOWER ? q : p;
+            // the triangles: zeros above, a unit diagonal as 1, the identity beyond the size
+            N1[i][j] = (i < n1 && j < i) ? a[u] : (i == j ? ((i < n1 && !unit) ? a[u] : 1.0) : 0.0);
+            N2[i][j] = (i < n2 && j < i) ? b[u] : (i == j ? ((i < n2 && !unit) ? b[u] : 1.0) : 0.0);
+            S21[i][j] = (i < n2 && j < n1) ? c[u] : 0.0;
+        }
+        // (1): the identity's columns 16·wave .. 16·wave + 15 as this wave's vectors
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = (lane >> 4) + 4 * u, q = lane & 15;
+            X[wave][e][q] = (e == 16 * wave + q && e < n1) ? 1.0 : 0.0;
+        }
+    }
+    __syncthreads();
+    solve64<double, true>(N1, X[wave], n1, unit, lane);
+    __syncthreads();
+    // (2) row block `wave` of A21: −A21·A11⁻¹ (column j of A11⁻¹ is vector j % 16 of wave j / 16)
+    {
+        d4 acc[4];
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) acc[jb] = d4{0, 0, 0, 0};
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 16 * kb + 4 * kk + (lane >> 4);
+                const double av = S21[16 * wave + (lane & 15)][k];
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb)
+                    acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, X[jb][k][lane & 15], acc[jb], 0, 0, 0);
+            }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) S21[16 * wave + (lane >> 4) + 4 * v][16 * jb + (lane & 15)] = -acc[jb][v];
+    }
+    // A11⁻¹ out (its triangle; a unit diagonal stays as it is)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = (lane >> 4) + 4 * u, q = lane & 15, j = 16 * wave + q;
+        if (e < n1 && j < n1 && (unit ? e > j : e >= j)) A[e * si + j * sj] = X[wave][e][q];
+    }
+    __syncthreads();
+    // (3) the columns of A21 as vectors: X[w][e][q] = A21(e, 16w + q)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = (lane >> 4) + 4 * u, q = lane & 15;
+        X[wave][e][q] = S21[e][16 * wave + q];
+    }
+    __builtin_amdgcn_wave_barrier();
+    solve64<double, true>(N2, X[wave], n2, unit, lane);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = (lane >> 4) + 4 * u, q = lane & 15, j = 16 * wave + q;
+        if (e < n2 && j < n1) A21[e * si + j * sj] = X[wave][e][q];
+    }
+    __builtin_amdgcn_wave_barrier();
+    // (4)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = (lane >> 4) + 4 * u, q = lane & 15;
+        X[wave][e][q] = (e == 16 * wave + q && e < n2) ? 1.0 : 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    solve64<double, true>(N2, X[wave], n2, unit, lane);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = (lane >> 4) + 4 * u, q = lane & 15, j = 16 * wave + q;
+        if (e < n2 && j < n2 && (unit ? e > j : e >= j)) A22[e * si + j * sj] = X[wave][e][q];
+    }
+}
+
+static void trtri128(Ctx &c, bool lower, bool unit, int n, double *A, long long lda) {
+    if (plan_record(c, PK_TRTI2, n, n, n)) return;
+    const int *abort = c.abort_on_info ? &c.dstat->info : nullptr;
+    trace_kernel_begin(c);
+    if (lower)
+        rl_launch(c, trtri128_k<true>, dim3(1), dim3(256), 0, n, (int)unit, A, lda, abort);
+    else
+        rl_launch(c, trtri128_k<false>, dim3(1), dim3(256), 0, n, (int)unit, A, lda, abort);
+    RL_CHECK(hipGetLastError());
+    trace_kernel_end(c, PK_TRTI2, (double)n * n * n / 3.0, 16.0 * n * n);
+}
+
+// ---------------------------------------------------------------------------
+// lauum of a whole triangle of 64 < t <= 128 rows in one launch (the
+// recursion's bottom node): entry (i, j), i >= j, of Lᵀ·L is the sum over
+// k >= i of l_ki·l_kj (U·Uᵀ is the same with L = Uᵀ). The triangle is staged
+// in LDS before anything is written, so the result overwrites it in place;
+// 16×16 tiles of the result's lower triangle go to the four waves, each the
+// sum on the FP64 matrix cores over k from its tile row on.
+// ---------------------------------------------------------------------------
+template <bool LOWER>
+__global__ __launch_bounds__(256) void lauum128_k(int t, double *__restrict__ A, long long lda, const int *abort) {
+    if (abort && *abort) return;
+    __shared__ double L[128][129];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    {
+        // element (i, j) of L: A[i + j·lda] (lower) or A[j + i·lda] (L = Uᵀ);
+        // the contiguous index runs fastest across the threads
+        double v[64];
+#pragma unroll
+        for (int u = 0; u < 64; ++u) {
+            const int idx = tid + 256 * u, a = idx & 127, b = idx >> 7;
+            const int i = LOWER ? a : b, j = LOWER ? b : a;
+            v[u] = A[LOWER ? min(i, t - 1) + (long long)min(j, t - 1) * lda
+                           : min(j, t - 1) + (long long)min(i, t - 1) * lda];
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int u = 0; u < 64; ++u) {
+            const int idx = tid + 256 * u, a = idx & 127, b = idx >> 7;
+            const int i = LOWER ? a : b, j = LOWER ? b : a;
+            L[i][j] = (i < t && j < t && j <= i) ? v[u] : 0.0;
+        }
+    }
+    __syncthreads();
+    const int nt = (t + 15) / 16, ntiles = nt * (nt + 1) / 2;
+    for (int tt = wave; tt < ntiles; tt += 4) {
+        int I = 0, a0 = 0;
+        while (a0 + I + 1 <= tt) { a0 += I + 1; ++I; }
+        const int J = tt - a0;
+        d4 acc = d4{0, 0, 0, 0};
+        for (int k0 = 16 * I; k0 < 16 * nt; k0 += 4) {
+            const int k = k0 + (lane >> 4);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(L[k][16 * I + (lane & 15)], L[k][16 * J + (lane & 15)], acc,
+                                                       0, 0, 0);
+        }
+        // FP64 16×16×4 result layout: element v of lane l is D[l/16 + 4v][l%16]
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * I + (lane >> 4) + 4 * v, j = 16 * J + (lane & 15);
+            if (i < t && j <= i) {
+                if (LOWER) A[i + (long long)j * lda] = acc[v];
+                else A[j + (long long)i * lda] = acc[v];
+            }
+        }
+    }
+}
+
+static void lauum128(Ctx &c, bool lower, int t, double *A, long long lda) {
+    if (plan_record(c, PK_LAUU2, t, t, t)) return;
+    const int *abort = c.abort_on_info ? &c.dstat->info : nullptr;
+    trace_kernel_begin(c);
+    if (lower)
+        rl_launch(c, lauum128_k<true>, dim3(1), dim3(256), 0, t, A, lda, abort);
+    else
+        rl_launch(c, lauum128_k<false>, dim3(1), dim3(256), 0, t, A, lda, abort);
+    RL_CHECK(hipGetLastError());
+    trace_kernel_end(c, PK_LAUU2, (double)t * t * t / 3.0, 16.0 * t * t);
+}
+
+// ---------------------------------------------------------------------------
 // First exact zero on the diagonal (1-based) into the call's info, 0 if none.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void diag_zero_k(long long n, const double *__restrict__ A, long long lda,
@@ -455,6 +644,10 @@ void trtri_rec(Ctx &c, char uplo, char diag, long long n, double *A, long long l
         trti2_leaf(c, lower, isc(diag, 'U'), (int)n, A, lda);
         return;
     }
+    if (n <= 2 * kTrsmLeaf && !(c.plan && c.plan_leaf > 0)) {
+        trtri128(c, lower, isc(diag, 'U'), (int)n, A, lda);   // the bottom node in one launch
+        return;
+    }
     const long long n1 = split_size(n), n2 = n - n1;
     double *A22 = A + n1 + n1 * lda;
     c.level++;
@@ -479,6 +672,10 @@ void lauum_rec(Ctx &c, char uplo, long long n, double *A, long long lda) {
     const bool lower = isc(uplo, 'L');
     if (n <= leaf) {
         lauu2(c, lower, (int)n, A, lda);
+        return;
+    }
+    if (n <= 2 * kTrsmLeaf && !(c.plan && c.plan_leaf > 0)) {
+        lauum128(c, lower, (int)n, A, lda);   // the bottom node in one launch
         return;
     }
     const long long n1 = split_size(n), n2 = n - n1;
