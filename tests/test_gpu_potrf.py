@@ -76,6 +76,20 @@ def test_not_positive_definite(orc, n, k):
     assert _run(nanm)[1] == k
 
 
+@pytest.mark.parametrize("n,k", [(200, 30), (200, 70), (130, 100)])
+def test_not_positive_definite_upper(orc, n, k):
+    """'U' failures inside the one-launch bottom node: in its first block
+    (200, 30), its second (200, 70), and a 66-row node split 33 + 33
+    (130, 100)."""
+    a = gen.spd_bbt(n, seed=5)
+    a[k - 1, k - 1] = -1.0
+    f, info = _run(a, "U")
+    ref, rinfo = orc.potrf(a, "U")
+    assert info == rinfo == k
+    if k > 1:
+        assert rel_fro(np.triu(f[: k - 1, : k - 1]), np.triu(ref[: k - 1, : k - 1])) <= 1e-12
+
+
 def test_zero_and_one():
     import torch
 
