@@ -64,6 +64,8 @@ void relapack_finalize(void);
  * info = k > 0: the leading minor of order k is not positive definite (its
  * pivot is <= 0 or NaN); every kernel after the failing leaf returns at once,
  * so columns before k hold the factor and column k holds its updated pivot.
+ * The recursion's leaves are 64 columns; its bottom node (64 < n <= 128:
+ * two leaves, the solve and the update between them) runs as one launch.
  * Errors: uplo -1, n -2, lda -4.
  */
 void relapack_dpotrf(char uplo, int n, double *A, int lda, int *info);
@@ -279,7 +281,8 @@ void relapack_dtrmm(char side, char uplo, char transa, char diag, int m, int n, 
 /*
  * Inverse of a triangular matrix in place (xtrtri, Sec. 5; the recursive
  * algorithm of Sec. 3, Fig. recursive_alg: invert A_TL, A_BL := A_BL·A_TL,
- * A_BL := −A_BR⁻¹·A_BL, invert A_BR; unblocked below 64). uplo selects the
+ * A_BL := −A_BR⁻¹·A_BL, invert A_BR; unblocked below 64, the bottom node
+ * of at most 128 rows in one launch). uplo selects the
  * triangle; diag = 'U': unit diagonal, not read and not written. The strict
  * other triangle is neither read nor written.
  * info = i > 0: A(i,i) is exactly zero (diag = 'N'); this is checked before
@@ -292,8 +295,9 @@ void relapack_dtrtri(char uplo, char diag, int n, double *A, int lda, int *info)
  * Product of a triangle with its own transpose in place (xlauum, Sec. 5):
  * uplo = 'L': the lower triangle of A becomes that of Lᵀ·L; uplo = 'U': the
  * upper triangle becomes that of U·Uᵀ. Recursive: lauum(A_TL), A_TL +=
- * A_BLᵀ·A_BL (matrix-core SYRK), A_BL := A_BRᵀ·A_BL (trmm), lauum(A_BR).
- * The strict other triangle is neither read nor written.
+ * A_BLᵀ·A_BL (matrix-core SYRK), A_BL := A_BRᵀ·A_BL (trmm), lauum(A_BR);
+ * a triangle of at most 128 rows in one launch. The strict other triangle is
+ * neither read nor written.
  * Errors: uplo -1, n -2, lda -4.
  */
 void relapack_dlauum(char uplo, int n, double *A, int lda, int *info);
@@ -431,8 +435,10 @@ int relapack_trace_collect(double *out, int cap);
 
 /* The kernel-call sequence of one factorization without launching anything
  * (no GPU needed): routine "potrf_L", "potrf_U", "getrf", "trtri_L",
- * "trtri_U", "lauum_L" or "lauum_U"; leaf > 0
- * overrides every crossover size. Writes up to cap records of 5 int64
+ * "trtri_U", "lauum_L" or "lauum_U"; leaf > 0 overrides every crossover
+ * size and records the plain recursion at it (leaf = 0: the library's own
+ * sizes, with the one-launch bottom nodes as one record each of kind 1, 13
+ * or 15). Writes up to cap records of 5 int64
  * {kind, depth, m, n, k} to rec; returns the total number of calls. */
 long long relapack_plan(const char *routine, long long m, long long n, int leaf, long long *rec,
                         long long cap);
