@@ -160,41 +160,38 @@ struct TrmmBlkArgs {
     const int *abort;
 };
 
-template <bool LOWER>
+template <bool LOWER, int TS>
 __global__ __launch_bounds__(256) void trmm_blk_k(TrmmBlkArgs a) {
+    constexpr int MI = TS / 32, EL = TS / 16;   // 16-blocks per wave and side, staged elements per thread
     if (a.abort && *a.abort) return;
-    __shared__ double Ns[2][16][65];   // [k][row]
-    __shared__ double Xs[2][16][65];   // [k][vector]
+    __shared__ double Ns[2][16][TS + 1];   // [k][row]
+    __shared__ double Xs[2][16][TS + 1];   // [k][vector]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, t = a.t;
     const int rt = (int)(blockIdx.x % a.tiles_e);
     const int te = LOWER ? a.tiles_e - 1 - rt : rt;
-    const long long v0 = (long long)(blockIdx.x / a.tiles_e) * 64;
-    const int e0 = 64 * te;
-    const int kb = LOWER ? 0 : e0, ke = LOWER ? min(e0 + 64, t) : t;
-    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const long long v0 = (long long)(blockIdx.x / a.tiles_e) * TS;
+    const int e0 = TS * te;
+    const int kb = LOWER ? 0 : e0, ke = LOWER ? min(e0 + TS, t) : t;
+    const int wm = (wave & 1) * (TS / 2), wn = (wave >> 1) * (TS / 2);
     const bool tcol = a.ti == 1, xcol = a.xe == 1;   // contiguous along the rows / along k
-    double rn[4], rx[4];
-    auto n_coord = [&](int u, int &i, int &k) {
-        if (tcol) { i = tid & 63; k = (tid >> 6) + 4 * u; }
-        else { k = tid & 15; i = (tid >> 4) + 16 * u; }
-    };
-    auto x_coord = [&](int u, int &k, int &v) {
-        if (xcol) { k = tid & 15; v = (tid >> 4) + 16 * u; }
-        else { v = tid & 63; k = (tid >> 6) + 4 * u; }
-    };
+    double rn[EL], rx[EL];
+    // staging coordinates (branch-free selects: reference outputs chosen by a
+    // branch end up in scratch): row i / vector v and k of element u
+    auto n_i = [&](int u) { return tcol ? tid % TS : (tid >> 4) + 16 * u; };
+    auto n_k = [&](int u) { return tcol ? tid / TS + (256 / TS) * u : tid & 15; };
+    auto x_k = [&](int u) { return xcol ? tid & 15 : tid / TS + (256 / TS) * u; };
+    auto x_v = [&](int u) { return xcol ? (tid >> 4) + 16 * u : tid % TS; };
     auto load = [&](int k0) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            int i, k;
-            n_coord(u, i, k);
+        for (int u = 0; u < EL; ++u) {
+            const int i = n_i(u), k = n_k(u);
             const int gi = e0 + i, gk = k0 + k;
             const bool in = gi < t && gk < t && (LOWER ? gk <= gi : gk >= gi);
             rn[u] = !in ? 0.0 : ((gk == gi && a.unit) ? 1.0 : a.T[gi * a.ti + gk * a.tj]);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            int k, v;
-            x_coord(u, k, v);
+        for (int u = 0; u < EL; ++u) {
+            const int k = x_k(u), v = x_v(u);
             const int gk = k0 + k;
             const long long gv = v0 + v;
             rx[u] = (gk < ke && gv < a.nvec) ? a.X[gk * a.xe + gv * a.xr] : 0.0;
@@ -202,23 +199,19 @@ __global__ __launch_bounds__(256) void trmm_blk_k(TrmmBlkArgs a) {
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            int i, k;
-            n_coord(u, i, k);
-            Ns[buf][k][i] = rn[u];
+        for (int u = 0; u < EL; ++u) {
+            Ns[buf][n_k(u)][n_i(u)] = rn[u];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            int k, v;
-            x_coord(u, k, v);
-            Xs[buf][k][v] = rx[u];
+        for (int u = 0; u < EL; ++u) {
+            Xs[buf][x_k(u)][x_v(u)] = rx[u];
         }
     };
-    d4 acc[2][2];
+    d4 acc[MI][MI];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0, 0, 0, 0};
+        for (int j = 0; j < MI; ++j) acc[i][j] = d4{0, 0, 0, 0};
     const int KT = (ke - kb + 15) / 16;   // >= 1
     load(kb);
     store(0);
@@ -229,15 +222,15 @@ __global__ __launch_bounds__(256) void trmm_blk_k(TrmmBlkArgs a) {
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int kr = 4 * ks + (lane >> 4);
-            double av[2], bv[2];
+            double av[MI], bv[MI];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) av[i] = Ns[buf][kr][wm + 16 * i + (lane & 15)];
+            for (int i = 0; i < MI; ++i) av[i] = Ns[buf][kr][wm + 16 * i + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) bv[j] = Xs[buf][kr][wn + 16 * j + (lane & 15)];
+            for (int j = 0; j < MI; ++j) bv[j] = Xs[buf][kr][wn + 16 * j + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < MI; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < MI; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
         }
         if (kt + 1 < KT) store(buf ^ 1);
@@ -245,9 +238,9 @@ __global__ __launch_bounds__(256) void trmm_blk_k(TrmmBlkArgs a) {
     }
     // FP64 16×16×4 result layout: element v of lane l is D[l/16 + 4v][l%16]
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < MI; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int e = e0 + wm + 16 * i + (lane >> 4) + 4 * v;
@@ -283,13 +276,20 @@ static void trmm_blk(Ctx &c, bool lower_eff, bool unit, int t, const double *T, 
     hipLaunchKernelGGL(trmm_copy_k, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, c.stream, B, se, sr, X, t,
                        nvec, abort);
     RL_CHECK(hipGetLastError());
-    TrmmBlkArgs a{unit ? 1 : 0, t, (t + 63) / 64, T, ti, tj, X, se == 1 ? 1 : nvec, se == 1 ? (long long)t : 1,
+    // 64×64 output tiles, or 32×32 ones when the 64-tiles would not give every
+    // CU two workgroups
+    const bool small = (long long)((t + 63) / 64) * ((nvec + 63) / 64) < 2LL * c.num_cu;
+    const int ts = small ? 32 : 64;
+    TrmmBlkArgs a{unit ? 1 : 0, t, (t + ts - 1) / ts, T, ti, tj, X, se == 1 ? 1 : nvec, se == 1 ? (long long)t : 1,
                   B, se, sr, nvec, alpha, abort};
-    const dim3 grid((unsigned)((long long)a.tiles_e * ((nvec + 63) / 64)));
-    if (lower_eff)
-        hipLaunchKernelGGL(trmm_blk_k<true>, grid, dim3(256), 0, c.stream, a);
-    else
-        hipLaunchKernelGGL(trmm_blk_k<false>, grid, dim3(256), 0, c.stream, a);
+    const dim3 grid((unsigned)((long long)a.tiles_e * ((nvec + ts - 1) / ts)));
+    if (small) {
+        if (lower_eff) hipLaunchKernelGGL((trmm_blk_k<true, 32>), grid, dim3(256), 0, c.stream, a);
+        else hipLaunchKernelGGL((trmm_blk_k<false, 32>), grid, dim3(256), 0, c.stream, a);
+    } else {
+        if (lower_eff) hipLaunchKernelGGL((trmm_blk_k<true, 64>), grid, dim3(256), 0, c.stream, a);
+        else hipLaunchKernelGGL((trmm_blk_k<false, 64>), grid, dim3(256), 0, c.stream, a);
+    }
     RL_CHECK(hipGetLastError());
     trace_end(c, PK_TRMM, (double)t * t * nvec, 8.0 * (t * t / 2.0 + 3.0 * t * nvec));
 }
