@@ -33,6 +33,8 @@
 #include "common.hpp"
 #include "wg.hpp"
 
+#include <algorithm>
+
 namespace rl {
 
 static inline bool isc(char a, char b) { return a == b || a == (char)(b + ('a' - 'A')); }
@@ -253,14 +255,15 @@ __global__ __launch_bounds__(256) void trmm_blk_k(TrmmBlkArgs a) {
 __global__ __launch_bounds__(256) void trmm_copy_k(const double *__restrict__ B, long long se, long long sr,
                                                    double *__restrict__ X, int t, long long nvec, const int *abort) {
     if (abort && *abort) return;
-    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (long long)t * nvec) return;
-    if (se == 1) {
-        const long long e = idx % t, r = idx / t;
-        X[idx] = B[e + r * sr];
-    } else {
-        const long long r = idx % nvec, e = idx / nvec;
-        X[idx] = B[e * se + r];
+    const long long nel = (long long)t * nvec, stride = (long long)gridDim.x * 256;
+    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < nel; idx += stride) {
+        if (se == 1) {
+            const long long e = idx % t, r = idx / t;
+            X[idx] = B[e + r * sr];
+        } else {
+            const long long r = idx % nvec, e = idx / nvec;
+            X[idx] = B[e * se + r];
+        }
     }
 }
 
@@ -273,8 +276,8 @@ static void trmm_blk(Ctx &c, bool lower_eff, bool unit, int t, const double *T, 
     const int *abort = c.abort_on_info ? &c.dstat->info : nullptr;
     trace_begin(c, PK_TRMM);
     const long long nel = (long long)t * nvec;
-    hipLaunchKernelGGL(trmm_copy_k, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, c.stream, B, se, sr, X, t,
-                       nvec, abort);
+    hipLaunchKernelGGL(trmm_copy_k, dim3((unsigned)std::min<long long>((nel + 255) / 256, 1LL << 20)), dim3(256), 0,
+                       c.stream, B, se, sr, X, t, nvec, abort);
     RL_CHECK(hipGetLastError());
     // 64×64 output tiles, or 32×32 ones when the 64-tiles would not give every
     // CU two workgroups
