@@ -23,12 +23,13 @@ void potrf_rec(Ctx &c, Mfma mode, char uplo, long long n, T *A, long long lda, l
         potf2<T>(c, uplo, (int)n, A, lda, off);
         return;
     }
-    // the bottom node in one launch, where its update runs in the working
-    // precision (not the mixed solver's FP16/BF16 operands) and no plan asks
-    // for another leaf size (a plan with an explicit crossover records the
-    // plain recursion at that crossover)
+    // the bottom node in one launch, unless a plan asks for another leaf size
+    // (a plan with an explicit crossover records the plain recursion at that
+    // crossover); its update runs in the storage precision, also under the
+    // mixed solver's FP16/BF16 operands (one 64×64×64 product per node, on a
+    // factor that only preconditions the refinement)
     const bool native = mode == (sizeof(T) == 8 ? Mfma::F64 : Mfma::F32);
-    if (native && !(c.plan && c.plan_leaf > 0) && n <= 2 * kCholLeaf) {
+    if ((native || sizeof(T) == 4) && !(c.plan && c.plan_leaf > 0) && n <= 2 * kCholLeaf) {
         potf2x2<T>(c, uplo, (int)n, A, lda, off);
         return;
     }
