@@ -138,6 +138,24 @@ def test_zgetrf_tall_panels(orc, m, n):
     assert rel_fro(_host(d), ref) <= 1e-10
 
 
+def test_zgetrf_panel_beyond_the_grid(orc):
+    """A panel of more rows than the chip's CUs can hold as 512-row workgroups
+    (140000 rows: 274 of them) is factored by the one-workgroup panel
+    instead, with its interchanges applied one by one."""
+    _setup()
+    import torch
+
+    m, n = 140000, 20
+    a = gen.general_complex(m, n, seed=17)
+    d = _dev(a)
+    piv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    assert rl.zgetrf(d, piv) == 0
+    ref, rpiv, info = orc.zgetrf(a)
+    assert info == 0
+    assert np.array_equal(piv.cpu().numpy(), rpiv)
+    assert rel_fro(_host(d), ref) <= 1e-10
+
+
 def test_zgetrf_tall_zero_pivot(orc):
     _setup()
     import torch
