@@ -26,11 +26,12 @@ def _tri(uplo):
 @pytest.mark.parametrize("uplo", ["L", "U"])
 @pytest.mark.parametrize("trans", ["N", "T"])
 @pytest.mark.parametrize("diag", ["N", "U"])
-@pytest.mark.parametrize("m,n", [(1, 1), (64, 64), (65, 33), (200, 130), (300, 257), (1030, 90)])
+@pytest.mark.parametrize("m,n", [(1, 1), (64, 64), (65, 33), (200, 130), (300, 257), (1030, 90), (1000, 2100)])
 def test_trmm(side, uplo, trans, diag, m, n):
     """Up to 64 rows the leaf; above, one launch per triangle of up to 1024
     rows (ragged tiles at 200, 257, 300) under the recursion's splits
-    (1030)."""
+    (1030, 2100), on 32×32 output tiles or, with enough of them (1000 rows
+    by 2100 vectors), 64×64 ones."""
     t = m if side == "L" else n
     tri = gen.triangular(t, uplo, "N", seed=t)
     stored = tri.copy(order="F")
